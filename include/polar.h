@@ -1,0 +1,203 @@
+/*
+ * polar.h -- C ABI of libpolarhip, a hybrid belief-propagation / CRC-aided
+ * successive-cancellation-list decoder of polar codes for AMD MI355X (gfx950).
+ *
+ * Method: Cammerer, Leible, Stahl, Hoydis, ten Brink, "Combining Belief
+ * Propagation and Successive Cancellation List Decoding of Polar Codes on a
+ * GPU Platform".  Sections cited below are that paper's.
+ *
+ * Conventions shared by every entry point
+ *   - N = 2^n is the block length, x = u G with G = F^{(x)n}, F = [[1,0],[1,1]],
+ *     natural index order (Sec. II, Fig. 1).
+ *   - A code has K information bits and c CRC bits; the k = K + c
+ *     non-frozen positions of u carry the K information bits followed by the
+ *     c CRC bits, in ascending index order; frozen positions hold 0.
+ *   - Bits are uint8 values 0/1, row-major, one row per frame.
+ *   - LLR = ln P(y|0)/P(y|1) (Sec. II-A): a positive LLR favours bit 0.
+ *   - "dev" marks a device pointer (e.g. from hipMalloc or a torch tensor),
+ *     "host" a host pointer.  The caller owns every batch buffer and every
+ *     workspace; the library never allocates during a decode call.
+ *   - Every decode/encode call only validates its arguments and enqueues work
+ *     on `stream`; results are valid once the stream has been synchronised.
+ *     Argument errors are reported synchronously before anything is enqueued.
+ *     A device failure is reported as POLAR_ERR_DEVICE by the call that
+ *     observes it.  No C++ exception crosses this interface.
+ *   - Calls on different streams may run concurrently if they use disjoint
+ *     output buffers and workspaces; a polar_code is immutable after
+ *     construction and may be shared.
+ */
+#ifndef POLAR_H
+#define POLAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    POLAR_OK = 0,
+    POLAR_ERR_INVALID_ARG = 1, /* a pointer, size or parameter is out of range */
+    POLAR_ERR_UNSUPPORTED = 2, /* valid request this build does not implement   */
+    POLAR_ERR_NO_MEMORY = 3,   /* host or device allocation failed (construction only) */
+    POLAR_ERR_DEVICE = 4,      /* a HIP runtime call failed                       */
+    POLAR_ERR_WORKSPACE = 5    /* workspace pointer missing or too small          */
+} polar_status;
+
+/* Thread-local, human-readable description of the last error on this thread
+ * (empty string after success).  The pointer stays valid until the next call
+ * on the same thread. */
+const char* polar_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Code description and construction (Sec. II).
+ * The paper decodes a given, arbitrary frozen vector f.  When `frozen` is NULL
+ * the library chooses it by the Gaussian approximation of density evolution
+ * (Chung, Richardson, Urbanke 2001) at `design_ebn0_db`, with code rate K/N,
+ * keeping the k = K + c most reliable positions (ties: the higher index is
+ * taken as more reliable).
+ * ------------------------------------------------------------------------- */
+typedef struct polar_code polar_code;
+
+typedef struct {
+    int32_t N;              /* block length: power of two, 8 <= N <= 4096           */
+    int32_t K;              /* information bits, excluding the CRC, K >= 1          */
+    int32_t crc_bits;       /* c: 0, 8, 16 or 24                                     */
+    uint32_t crc_poly;      /* generator without its x^c term; 0 selects the default:
+                               0x07 (c=8), 0x1021 (c=16), 0x864CFB (c=24)           */
+    double design_ebn0_db;  /* design point of the construction (frozen == NULL)     */
+    const uint8_t* frozen;  /* host [N], 1 = frozen, or NULL; must contain exactly
+                               N - K - c ones                                        */
+} polar_code_desc;
+
+/* Builds a code and uploads its tables to the current HIP device.  On success
+ * *out receives a handle the caller releases with polar_free_code.  Errors:
+ * INVALID_ARG (bad sizes, mask with the wrong number of frozen positions),
+ * NO_MEMORY, DEVICE. */
+polar_status polar_build_code(const polar_code_desc* desc, polar_code** out);
+
+/* Host-only construction of the frozen mask that polar_build_code would use
+ * for (N, K, crc_bits, design_ebn0_db) without a given mask: writes N entries
+ * (1 = frozen) to host_mask.  Touches no device.  Errors: INVALID_ARG. */
+polar_status polar_construct_frozen(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_db,
+                                    uint8_t* host_mask);
+
+/* Releases the host and device tables of a code (NULL is ignored).  The caller
+ * must make sure no enqueued work still uses the code. */
+void polar_free_code(polar_code* code);
+
+/* Parameters of a built code: any pointer may be NULL. */
+polar_status polar_code_params(const polar_code* code, int32_t* N, int32_t* K,
+                               int32_t* crc_bits, uint32_t* crc_poly);
+
+/* Copies the frozen mask (1 = frozen) to host memory [N]. */
+polar_status polar_code_frozen(const polar_code* code, uint8_t* host_mask);
+
+/* ---------------------------------------------------------------------------
+ * Encoder (Sec. II, Fig. 1).
+ * info   dev [B][K]: information bits.
+ * u_out  dev [B][N] or NULL: the vector u (info, CRC, zeros on frozen positions).
+ * x_out  dev [B][N]: the codeword x = u G.
+ * ------------------------------------------------------------------------- */
+polar_status polar_encode(const polar_code* code, const uint8_t* info, int64_t B,
+                          uint8_t* u_out, uint8_t* x_out, hipStream_t stream);
+
+/* BPSK over AWGN for synthetic workloads: llr = 2 (1 - 2x + sqrt(s2) z) / s2,
+ * the LLR of Sec. II-A for a Gaussian channel.
+ * x dev [B][N] bits, z dev [B][N] unit-variance noise (the caller draws it),
+ * sigma2 dev [B] noise variance per frame, llr dev [B][N] output. */
+polar_status polar_channel_awgn(const uint8_t* x, const float* z, const float* sigma2, int64_t B,
+                                int32_t N, float* llr, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Belief-propagation decoder (Sec. II-B, Fig. 2).
+ * One iteration is a sweep of R messages over stages 2..n+1 followed by a
+ * sweep of L messages over stages n..1; inside a stage all N/2 processing
+ * elements update at once.  Initialisation L_{i,n+1} = LLR_i,
+ * R_{i,1} = llr_max * f_i; outputs LLR(u_i) = L_{i,1} + R_{i,1}.  The rule is
+ * min-sum, g(a,b) = sign(a) sign(b) min(|a|,|b|); channel LLRs and every
+ * computed message are clipped to +-llr_max.
+ * Early stop after each iteration (Sec. II-B): stop = 1 when the re-encoded
+ * estimate u_hat G equals the hard decision on LLR(x), stop = 2 when the CRC
+ * of u_hat holds, stop = 0 never.
+ * ok = CRC holds (stop = 2) or re-encoding check and CRC hold (stop 0, 1;
+ * without a CRC only the re-encoding check counts).
+ * Weighted (learned) form: when `weights` is given, the g term of every
+ * message computed in iteration t, direction d (0 = R, 1 = L), stage column s
+ * (0-based, the stage that pairs i with i + 2^s) and output node i is
+ * multiplied by weights[((t * 2 + d) * n + s) * N + i] before the addition and
+ * the clipping (additions use one fused multiply-add).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_iter;      /* i_max >= 1 (Sec. III)                               */
+    int32_t stop;          /* 0 none, 1 re-encoding check, 2 CRC                  */
+    float llr_max;         /* clipping level > 0 (20 in Sec. II-B)                */
+    int32_t rule;          /* 0 min-sum (the only rule this build runs on GPU)    */
+    const float* weights;  /* dev [weight_iters][2][n][N] or NULL                 */
+    int32_t weight_iters;  /* >= max_iter when weights != NULL                    */
+    int32_t variant;       /* kernel layout: 0 automatic, else a value returned by
+                              polar_bp_variants                                   */
+} bp_params;
+
+/* llr    dev [B][N] channel LLRs (float32).
+ * u_hat  dev [B][N] hard decisions on LLR(u) (frozen positions 0).
+ * llr_u  dev [B][N] or NULL: soft output LLR(u) = L_{i,1} + R_{i,1} (Sec. II-B).
+ * iters  dev [B] or NULL: iterations run (1..max_iter).
+ * ok     dev [B]: verdict as defined above. */
+polar_status bp_decode_batch(const polar_code* code, const float* llr, int64_t B,
+                             const bp_params* params, uint8_t* u_hat, float* llr_u,
+                             int32_t* iters, uint8_t* ok, hipStream_t stream);
+
+/* Kernel layouts of the BP decoder available for a block length: writes up to
+ * `cap` variant ids to `ids` and their count to *count.  Used by the autotuner. */
+polar_status polar_bp_variants(int32_t N, int32_t* ids, int32_t cap, int32_t* count);
+
+/* ---------------------------------------------------------------------------
+ * CRC-aided successive-cancellation list decoder (Sec. II-A), LLR based, min-sum
+ * path metrics: a path's metric grows by |LLR(u_i)| whenever its decision
+ * differs from the hard decision.  Frozen bits do not branch; at each
+ * information bit every path spawns both values and the L candidates of
+ * smallest (metric, parent list position, bit) survive, in that order (the
+ * "pruned pseudo sort" made a strict total order).  The result is the
+ * smallest-metric path whose CRC holds, else the smallest-metric path.
+ * L: 1..32, a power of two.
+ * frame_ids  dev [B] or NULL: decode frames frame_ids[0..B) of `llr` and write
+ *            row frame_ids[q] of the outputs (NULL: frames 0..B-1).
+ * u_hat dev rows [N], crc_ok dev [rows], pm dev [rows] or NULL (final metric).
+ * ws / ws_bytes: workspace of at least polar_workspace_size(code, B, L, NULL)
+ * bytes (may be NULL when that size is 0).
+ * ------------------------------------------------------------------------- */
+polar_status scl_decode_batch(const polar_code* code, const float* llr, int64_t B, int32_t L,
+                              const int32_t* frame_ids, uint8_t* u_hat, uint8_t* crc_ok,
+                              float* pm, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Hybrid decoder (Sec. III, Fig. 3): BP with params->max_iter iterations and
+ * the params->stop rule on every frame; frames whose verdict is not ok are
+ * compacted into a queue on the device ("copy failed CWs to buffer") and
+ * decoded again from their channel LLRs by the CA-SCL decoder with list size
+ * L.  No host round trip: the queue length stays on the device.
+ * info_hat  dev [B][K]: information bits of the kept result.
+ * used_scl  dev [B] or NULL: 1 when the frame went to the list decoder.
+ * stats     dev int64 [8] or NULL, accumulated (not cleared):
+ *           [0] frames, [1] BP ok, [2] SCL frames, [3] BP iterations summed,
+ *           [4] SCL frames whose CRC failed, [5..7] reserved (0).
+ * ------------------------------------------------------------------------- */
+polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64_t B,
+                                 const bp_params* params, int32_t L, uint8_t* info_hat,
+                                 uint8_t* used_scl, int64_t* stats, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* Workspace bytes needed by scl_decode_batch (params == NULL) or
+ * hybrid_decode_batch (params != NULL) for B frames and list size L. */
+polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,
+                                  const bp_params* params, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLAR_H */

@@ -1,0 +1,267 @@
+"""Thin Python binding of libpolarhip (the C ABI in include/polar.h).
+
+Argument marshalling only: every function here checks tensor shapes, dtypes
+and devices, takes raw device pointers and the current HIP stream from torch,
+and calls the entry point of the same name.  All decoding runs in the HIP
+kernels of the library.  There is no fallback: if the library is missing the
+import of this module's functions raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpolarhip.so")
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "NO_MEMORY", 4: "DEVICE", 5: "WORKSPACE"}
+DEFAULT_POLY = {0: 0, 8: 0x07, 16: 0x1021, 24: 0x864CFB}
+
+
+class PolarError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class polar_code_desc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("crc_bits", C.c_int32), ("crc_poly", C.c_uint32),
+                ("design_ebn0_db", C.c_double), ("frozen", C.POINTER(C.c_uint8))]
+
+
+class bp_params(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("stop", C.c_int32), ("llr_max", C.c_float), ("rule", C.c_int32),
+                ("weights", C.c_void_p), ("weight_iters", C.c_int32), ("variant", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpolarhip.so (built by build.py); raise if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libpolarhip.so not found at {LIB_PATH}: run __graft_entry__.build() "
+                               "or python paper_1609_09358_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
+        L.polar_last_error.restype = C.c_char_p
+        L.polar_last_error.argtypes = []
+        sig = {
+            "polar_build_code": [C.POINTER(polar_code_desc), C.POINTER(vp)],
+            "polar_construct_frozen": [i32, i32, i32, C.c_double, C.POINTER(C.c_uint8)],
+            "polar_code_params": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(u32)],
+            "polar_code_frozen": [vp, C.POINTER(C.c_uint8)],
+            "polar_encode": [vp, vp, i64, vp, vp, vp],
+            "polar_channel_awgn": [vp, vp, vp, i64, i32, vp, vp],
+            "bp_decode_batch": [vp, vp, i64, C.POINTER(bp_params), vp, vp, vp, vp, vp],
+            "polar_bp_variants": [i32, C.POINTER(i32), i32, C.POINTER(i32)],
+            "scl_decode_batch": [vp, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
+            "hybrid_decode_batch": [vp, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp],
+            "polar_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.polar_free_code.argtypes = [vp]
+        L.polar_free_code.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise PolarError(status, lib().polar_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape, name):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+# --------------------------------------------------------------------------- codes
+
+class PolarCode:
+    """Owner of a polar_code handle (frozen set and device tables)."""
+
+    def __init__(self, N, K, crc_bits=0, crc_poly=0, design_ebn0_db=2.0, frozen=None):
+        d = polar_code_desc()
+        d.N, d.K, d.crc_bits = N, K, crc_bits
+        d.crc_poly = crc_poly
+        d.design_ebn0_db = design_ebn0_db
+        self._frozen_in = None
+        if frozen is not None:
+            self._frozen_in = np.ascontiguousarray(frozen, dtype=np.uint8)
+            d.frozen = self._frozen_in.ctypes.data_as(C.POINTER(C.c_uint8))
+        h = C.c_void_p()
+        _check(lib().polar_build_code(C.byref(d), C.byref(h)))
+        self.handle = h
+        n_, k_, c_, p_ = C.c_int32(), C.c_int32(), C.c_int32(), C.c_uint32()
+        _check(lib().polar_code_params(h, C.byref(n_), C.byref(k_), C.byref(c_), C.byref(p_)))
+        self.N, self.K, self.crc_bits, self.crc_poly = n_.value, k_.value, c_.value, p_.value
+        self.n = self.N.bit_length() - 1
+        self.k = self.K + self.crc_bits
+        mask = np.zeros(self.N, np.uint8)
+        _check(lib().polar_code_frozen(h, mask.ctypes.data_as(C.POINTER(C.c_uint8))))
+        self.frozen = mask
+        self.info_pos = np.where(mask == 0)[0]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.polar_free_code(h)
+            self.handle = None
+
+
+def polar_construct_frozen(N, K, crc_bits=0, design_ebn0_db=2.0):
+    """Frozen mask (1 = frozen) of the library's construction, computed on the host."""
+    mask = np.zeros(N, np.uint8)
+    _check(lib().polar_construct_frozen(N, K, crc_bits, design_ebn0_db, mask.ctypes.data_as(C.POINTER(C.c_uint8))))
+    return mask
+
+
+def polar_build_code(N, K, crc_bits=0, crc_poly=0, design_ebn0_db=2.0, frozen=None) -> PolarCode:
+    return PolarCode(N, K, crc_bits, crc_poly, design_ebn0_db, frozen)
+
+
+def make_bp_params(max_iter=100, stop=1, llr_max=20.0, weights=None, variant=0, rule=0):
+    p = bp_params()
+    p.max_iter, p.stop, p.llr_max, p.rule = int(max_iter), int(stop), float(llr_max), int(rule)
+    p.weights = None if weights is None else weights.data_ptr()
+    p.weight_iters = 0 if weights is None else int(weights.shape[0])
+    p.variant = int(variant)
+    return p
+
+
+# --------------------------------------------------------------------------- entry points
+
+def polar_encode(code: PolarCode, info: torch.Tensor, want_u=False):
+    B = info.shape[0]
+    _dev(info, torch.uint8, (B, code.K), "info")
+    x = torch.empty((B, code.N), dtype=torch.uint8, device=info.device)
+    u = torch.empty_like(x) if want_u else None
+    _check(lib().polar_encode(code.handle, _ptr(info), B, _ptr(u), _ptr(x), _stream()))
+    return (u, x) if want_u else x
+
+
+def polar_channel_awgn(x: torch.Tensor, z: torch.Tensor, sigma2: torch.Tensor) -> torch.Tensor:
+    B, N = x.shape
+    _dev(x, torch.uint8, (B, N), "x")
+    _dev(z, torch.float32, (B, N), "z")
+    _dev(sigma2, torch.float32, (B,), "sigma2")
+    llr = torch.empty((B, N), dtype=torch.float32, device=x.device)
+    _check(lib().polar_channel_awgn(_ptr(x), _ptr(z), _ptr(sigma2), B, N, _ptr(llr), _stream()))
+    return llr
+
+
+def bp_decode_batch(code: PolarCode, llr: torch.Tensor, max_iter=100, stop=1, llr_max=20.0, weights=None,
+                    variant=0, soft=False, out=None):
+    B = llr.shape[0]
+    _dev(llr, torch.float32, (B, code.N), "llr")
+    if weights is not None:
+        _dev(weights, torch.float32, (weights.shape[0], 2, code.n, code.N), "weights")
+    dev = llr.device
+    if out is None:
+        out = dict(u_hat=torch.empty((B, code.N), dtype=torch.uint8, device=dev),
+                   iters=torch.empty(B, dtype=torch.int32, device=dev),
+                   ok=torch.empty(B, dtype=torch.uint8, device=dev))
+        if soft:
+            out["llr_u"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
+    p = make_bp_params(max_iter, stop, llr_max, weights, variant)
+    _check(lib().bp_decode_batch(code.handle, _ptr(llr), B, C.byref(p), _ptr(out["u_hat"]), _ptr(out.get("llr_u")),
+                                 _ptr(out["iters"]), _ptr(out["ok"]), _stream()))
+    return out
+
+
+def polar_bp_variants(N):
+    ids = (C.c_int32 * 8)()
+    cnt = C.c_int32()
+    _check(lib().polar_bp_variants(N, ids, 8, C.byref(cnt)))
+    return [ids[i] for i in range(cnt.value)]
+
+
+def polar_workspace_size(code: PolarCode, B, L, hybrid_params=None):
+    s = C.c_size_t()
+    p = C.byref(hybrid_params) if hybrid_params is not None else None
+    _check(lib().polar_workspace_size(code.handle, B, L, p, C.byref(s)))
+    return s.value
+
+
+def scl_decode_batch(code: PolarCode, llr: torch.Tensor, L, frame_ids=None, out=None, workspace=None):
+    rows = llr.shape[0]
+    _dev(llr, torch.float32, (rows, code.N), "llr")
+    B = rows if frame_ids is None else frame_ids.shape[0]
+    if frame_ids is not None:
+        _dev(frame_ids, torch.int32, (B,), "frame_ids")
+    dev = llr.device
+    if out is None:
+        out = dict(u_hat=torch.zeros((rows, code.N), dtype=torch.uint8, device=dev),
+                   crc_ok=torch.zeros(rows, dtype=torch.uint8, device=dev),
+                   pm=torch.zeros(rows, dtype=torch.float32, device=dev))
+    need = polar_workspace_size(code, B, L)
+    if workspace is None and need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().scl_decode_batch(code.handle, _ptr(llr), B, L, _ptr(frame_ids), _ptr(out["u_hat"]),
+                                  _ptr(out["crc_ok"]), _ptr(out["pm"]), _ptr(workspace),
+                                  0 if workspace is None else workspace.numel(), _stream()))
+    return out
+
+
+class HybridDecoder:
+    """hybrid_decode_batch with its workspace kept between calls."""
+
+    def __init__(self, code: PolarCode, max_iter=200, L=8, stop=1, llr_max=20.0, weights=None, variant=0):
+        self.code, self.L = code, L
+        self.weights = weights
+        self.params = make_bp_params(max_iter, stop, llr_max, weights, variant)
+        self.workspace = None
+
+    def __call__(self, llr: torch.Tensor, out=None, stats=None):
+        return hybrid_decode_batch(self.code, llr, self.params, self.L, out=out, stats=stats, decoder=self)
+
+
+def hybrid_decode_batch(code: PolarCode, llr: torch.Tensor, params: bp_params, L: int, out=None, stats=None,
+                        workspace=None, decoder=None):
+    B = llr.shape[0]
+    _dev(llr, torch.float32, (B, code.N), "llr")
+    dev = llr.device
+    if out is None:
+        out = dict(info=torch.empty((B, code.K), dtype=torch.uint8, device=dev),
+                   used_scl=torch.empty(B, dtype=torch.uint8, device=dev))
+    if stats is not None:
+        _dev(stats, torch.int64, (8,), "stats")
+    need = polar_workspace_size(code, B, L, params)
+    if workspace is None and decoder is not None:
+        if decoder.workspace is None or decoder.workspace.numel() < need:
+            decoder.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        workspace = decoder.workspace
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().hybrid_decode_batch(code.handle, _ptr(llr), B, C.byref(params), L, _ptr(out["info"]),
+                                     _ptr(out["used_scl"]), _ptr(stats), _ptr(workspace), workspace.numel(),
+                                     _stream()))
+    return out
+
+
+EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
+            "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
+            "hybrid_decode_batch", "polar_workspace_size"]

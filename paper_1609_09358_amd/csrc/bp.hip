@@ -1,0 +1,463 @@
+// bp.hip -- batched min-sum belief-propagation decoder of polar codes
+// (Sec. II-B, Fig. 2), plain and weighted, with early stopping by the
+// re-encoding check or the CRC.
+//
+// Design (MI355X / gfx950).  Messages live in registers.  A frame of N = 2^n
+// nodes per stage is spread over T = N / V threads, each holding V = 2^r nodes
+// of every stage row.  Which r index bits a thread holds in registers changes
+// along the sweep: window k keeps bits [b_k, b_k + r) in registers and handles
+// the PE columns that pair those bits, so every butterfly is computed inside
+// one thread without communication.  Between windows the single row on the
+// boundary is re-laid out through LDS (one write and one read per value).
+// The LDS address of an index is a sum of per-bit coefficients chosen at
+// compile time so that, for both layouts of a boundary, the 32 lanes of a
+// half-wavefront hit 32 different banks and the register part of the address
+// is an immediate offset.  Boundaries whose layouts differ only inside one
+// wavefront need no barrier; the others are separated by a workgroup barrier.
+// When a frame needs fewer than 64 threads, one wavefront carries 64 / T
+// frames, each leaving the iteration loop on its own.
+//
+// Early stop (Sec. II-B): after each iteration the hard decisions on LLR(u)
+// and LLR(x) are packed into bit words (N / 64 bits per lane), u_hat is
+// re-encoded with shifts inside words and lane exchanges across words, and
+// compared with x_hat; the CRC test uses per-nibble syndrome tables.
+#include <type_traits>
+
+#include "internal.hpp"
+#include "bp_geom.hpp"
+
+namespace polarhip {
+namespace bp {
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for_rev(F&& f) {  // E-1 down to B
+    if constexpr (B < E) {
+        f(std::integral_constant<int, E - 1>{});
+        static_for_rev<B, E - 1>(f);
+    }
+}
+
+__device__ __forceinline__ float g_ms(float a, float b) {
+    float m = fminf(fabsf(a), fabsf(b));
+    uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
+    return __uint_as_float(__float_as_uint(m) | s);
+}
+
+__device__ __forceinline__ float clipf(float v, float m) { return fminf(fmaxf(v, -m), m); }
+
+// index bits of thread t in window k, register bits zero
+template <class G, int K>
+__device__ __forceinline__ int idx_base(int t) {
+    constexpr int b = G::wbase(K);
+    return (t & ((1 << b) - 1)) | ((t >> b) << (b + G::r));
+}
+
+// thread part of the LDS word address for boundary J in the layout of window K
+template <class G, int J, int K>
+__device__ __forceinline__ int lds_base(int t, int slot) {
+    int a = 0;
+#pragma unroll
+    for (int q = 0; q < G::P; ++q)
+        if ((t >> q) & 1) a += G::TAB.b[J].c[G::tpb(K, q)];
+#pragma unroll
+    for (int j = 0; j < G::SLOTB; ++j)
+        if ((slot >> j) & 1) a += G::TAB.b[J].c[G::n + j];
+    return a;
+}
+
+template <class G>
+__device__ __forceinline__ void frame_sync() {
+    if constexpr (G::NWAVES > 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// re-layout one row from window KF to window KT across boundary J
+template <class G, int J, int KF, int KT, bool ISR>
+__device__ __forceinline__ void transpose_row(float (&row)[G::V], float* tb, int base_from, int base_to) {
+    constexpr int buf = ISR ? G::TAB.b[J].buf_r : G::TAB.b[J].buf_l;
+    float* p = tb + buf;
+#pragma unroll
+    for (int v = 0; v < G::V; ++v) p[base_from + G::reg_off(J, KF, v)] = row[v];
+    if constexpr (G::TAB.b[J].cross) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int v = 0; v < G::V; ++v) row[v] = p[base_to + G::reg_off(J, KT, v)];
+}
+
+template <class G>
+__device__ __forceinline__ uint64_t load_bits(const uint8_t* src) {
+    // CB bytes (0/1) starting at src -> CB-bit word, bit j = byte j
+    uint64_t w = 0;
+    if constexpr (G::CB >= 4) {
+#pragma unroll
+        for (int q = 0; q < G::CB / 4; ++q) {
+            uint32_t d = reinterpret_cast<const uint32_t*>(src)[q];
+            uint32_t nib = ((d * 0x01020408u) >> 24) & 0xFu;
+            w |= (uint64_t)nib << (4 * q);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < G::CB; ++q) w |= (uint64_t)(src[q] & 1u) << q;
+    }
+    return w;
+}
+
+// u G == x on the packed words of one frame; every checker lane gets the answer
+template <class G>
+__device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t* xb, int lane) {
+    uint64_t u = load_bits<G>(ub + lane * G::CB);
+    uint64_t x = load_bits<G>(xb + lane * G::CB);
+#pragma unroll
+    for (int d = 1; d < G::CB; d <<= 1) {
+        uint64_t m = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((p & d) == 0) m |= 1ull << p;
+        u ^= (u >> d) & m;
+    }
+#pragma unroll
+    for (int q = 1; q < G::TL; q <<= 1) {
+        uint64_t o = (uint64_t)__shfl_xor((unsigned long long)u, q, 64);
+        if ((lane & q) == 0) u ^= o;
+    }
+    uint64_t bad = __ballot(u != x);
+    if constexpr (G::TL < 64) {
+        const int grp = (__lane_id() / G::TL) * G::TL;
+        bad = (bad >> grp) & ((1ull << G::TL) - 1ull);
+    }
+    return bad == 0;
+}
+
+template <class G>
+__device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub, int lane) {
+    if (code.c == 0) return true;
+    uint64_t u = load_bits<G>(ub + lane * G::CB);
+    uint32_t s = 0;
+    const uint32_t* tab = code.syn_nib + (size_t)(lane * G::CB / 4) * 16;
+    if constexpr (G::CB >= 4) {
+#pragma unroll
+        for (int g = 0; g < G::CB / 4; ++g) s ^= tab[g * 16 + ((u >> (4 * g)) & 0xF)];
+    } else {
+        // fewer than 4 bits per lane: take the nibble from the lanes of the group
+        const int g = lane * G::CB / 4;
+        const int sh = (lane * G::CB) & 3;
+        uint32_t part = (uint32_t)(u << sh);
+        uint32_t nib = part;
+#pragma unroll
+        for (int q = 1; q < 4 / G::CB; ++q) nib |= __shfl_xor(part, q, 64);
+        s = (sh == 0) ? code.syn_nib[(size_t)g * 16 + (nib & 0xF)] : 0u;
+    }
+#pragma unroll
+    for (int q = 1; q < G::TL; q <<= 1) s ^= __shfl_xor(s, q, 64);
+    return s == 0;
+}
+
+template <int NLOG, int RLOG, bool WEIGHTED>
+__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
+    CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
+    const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
+    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out) {
+    using G = Geom<NLOG, RLOG>;
+    constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
+    __shared__ float tb[G::TAB.words];
+    __shared__ __attribute__((aligned(16))) uint8_t ubytes[G::FPW * N];
+    __shared__ __attribute__((aligned(16))) uint8_t xbytes[G::FPW * N];
+
+    const int tid = threadIdx.x;
+    const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
+    const int slot = (G::T < 64) ? (tid >> G::P) : 0;
+    const int64_t frame = (int64_t)blockIdx.x * G::FPW + slot;
+    if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
+    const int lane = (G::T < 64) ? t : (tid & 63);
+    uint8_t* ub = ubytes + slot * N;
+    uint8_t* xb = xbytes + slot * N;
+
+    // LDS bases of this thread for each boundary, on both sides
+    int bfrom[G::NB > 0 ? G::NB : 1], bto[G::NB > 0 ? G::NB : 1];
+    static_for<0, G::NB>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        bfrom[j] = lds_base<G, j, j>(t, slot);
+        bto[j] = lds_base<G, j, j + 1>(t, slot);
+    });
+
+    // messages: row rho of L / R, each V values in the layout of the window
+    // that stores it
+    float Lm[n + 1][V];
+    float Rm[n + 1][V];
+    float prior[V];
+#pragma unroll
+    for (int s = 0; s <= n; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            Lm[s][v] = 0.0f;
+            Rm[s][v] = 0.0f;
+        }
+    const float* fl = llr + frame * N;
+    {
+        const int ib = idx_base<G, KL>(t);
+#pragma unroll
+        for (int v = 0; v < V; ++v) Lm[n][v] = clipf(fl[ib + (v << G::wbase(KL))], lmax);
+    }
+    uint32_t fmask = 0;  // frozen flags of this thread's nodes in window 0
+    {
+        const int ib = idx_base<G, 0>(t);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            int i = ib + v;
+            uint32_t f = (code.frozen_bits[i >> 5] >> (i & 31)) & 1u;
+            fmask |= f << v;
+            prior[v] = f ? lmax : 0.0f;
+        }
+    }
+
+    int it = 0;
+    bool gok = false, cok = false;
+    float L0[V];
+    while (true) {
+        const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * N : nullptr;
+        // ---------------- R sweep: columns 0..n-1
+        static_for<0, G::NWIN>([&](auto KC) {
+            constexpr int k = decltype(KC)::value;
+            const int ib = idx_base<G, k>(t);
+            static_for<G::cbeg(k), G::cend(k)>([&](auto SC) {
+                constexpr int s = decltype(SC)::value;
+                constexpr int q = s - G::wbase(k);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (v & (1 << q)) continue;
+                    const int v2 = v | (1 << q);
+                    const float r1 = (s == 0) ? prior[v] : Rm[s][v];
+                    const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
+                    const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
+                    const float gi = g_ms(r1, l2 + r2);
+                    const float gj = g_ms(r1, l1);
+                    if constexpr (WEIGHTED) {
+                        const float* w = Wit + (size_t)(0 * n + s) * N + ib;
+                        const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
+                        Rm[s + 1][v] = clipf(wi * gi, lmax);
+                        Rm[s + 1][v2] = clipf(__fmaf_rn(wj, gj, r2), lmax);
+                    } else {
+                        Rm[s + 1][v] = gi;  // |g| <= |r1| <= lmax: the clip is exact
+                        Rm[s + 1][v2] = clipf(gj + r2, lmax);
+                    }
+                }
+            });
+            if constexpr (k < G::NWIN - 1) {
+                transpose_row<G, k, k, k + 1, true>(Rm[G::cend(k)], tb, bfrom[k], bto[k]);
+            }
+        });
+        if (stop != 2) {
+            const int ib = idx_base<G, KL>(t);
+#pragma unroll
+            for (int v = 0; v < V; ++v) xb[ib + (v << G::wbase(KL))] = (Lm[n][v] + Rm[n][v]) < 0.0f ? 1 : 0;
+        }
+        // ---------------- L sweep: columns n-1..0
+        static_for_rev<0, G::NWIN>([&](auto KC) {
+            constexpr int k = decltype(KC)::value;
+            const int ib = idx_base<G, k>(t);
+            static_for_rev<G::cbeg(k), G::cend(k)>([&](auto SC) {
+                constexpr int s = decltype(SC)::value;
+                constexpr int q = s - G::wbase(k);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (v & (1 << q)) continue;
+                    const int v2 = v | (1 << q);
+                    const float r1 = (s == 0) ? prior[v] : Rm[s][v];
+                    const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
+                    const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
+                    const float gi = g_ms(l1, l2 + r2);
+                    const float gj = g_ms(r1, l1);
+                    if constexpr (WEIGHTED) {
+                        const float* w = Wit + (size_t)(1 * n + s) * N + ib;
+                        const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
+                        Lm[s][v] = clipf(wi * gi, lmax);
+                        Lm[s][v2] = clipf(__fmaf_rn(wj, gj, l2), lmax);
+                    } else {
+                        Lm[s][v] = gi;  // |g| <= |l1| <= lmax
+                        Lm[s][v2] = clipf(gj + l2, lmax);
+                    }
+                }
+            });
+            if constexpr (k > 0) {
+                transpose_row<G, k - 1, k, k - 1, false>(Lm[G::cbeg(k)], tb, bto[k - 1], bfrom[k - 1]);
+            }
+        });
+        // ---------------- decisions in window 0 (register bits are the low bits)
+        {
+            uint64_t pack = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                L0[v] = Lm[0][v];
+                const float lu = Lm[0][v] + prior[v];
+                const uint64_t bit = (((fmask >> v) & 1u) == 0 && lu < 0.0f) ? 1ull : 0ull;
+                pack |= bit << (8 * v);
+            }
+            uint8_t* dst = ub + idx_base<G, 0>(t);
+            if constexpr (V == 8) {
+                *reinterpret_cast<uint64_t*>(dst) = pack;
+            } else if constexpr (V == 4) {
+                *reinterpret_cast<uint32_t*>(dst) = (uint32_t)pack;
+            } else if constexpr (V == 2) {
+                *reinterpret_cast<uint16_t*>(dst) = (uint16_t)pack;
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) dst[v] = (uint8_t)(pack >> (8 * v));
+            }
+        }
+        ++it;
+        const bool last = it >= max_iter;
+        if (stop == 1) {
+            frame_sync<G>();
+            gok = reencode_check<G>(ub, xb, lane);
+            if (gok || last) {
+                cok = crc_check<G>(code, ub, lane);
+                break;
+            }
+        } else if (stop == 2) {
+            frame_sync<G>();
+            cok = crc_check<G>(code, ub, lane);
+            if (cok || last) break;
+        } else if (last) {
+            frame_sync<G>();
+            gok = reencode_check<G>(ub, xb, lane);
+            cok = crc_check<G>(code, ub, lane);
+            break;
+        }
+    }
+
+    // ---------------- outputs (window 0 layout: V consecutive nodes per thread)
+    {
+        const int ib = idx_base<G, 0>(t);
+        uint8_t* uo = u_hat + frame * N + ib;
+        const uint8_t* src = ub + ib;
+#pragma unroll
+        for (int v = 0; v < V; ++v) uo[v] = src[v];
+        if (llr_u) {
+            float* lo = llr_u + frame * N + ib;
+#pragma unroll
+            for (int v = 0; v < V; ++v) lo[v] = L0[v] + prior[v];
+        }
+        if (t == 0) {
+            if (iters_out) iters_out[frame] = it;
+            ok_out[frame] = (uint8_t)(stop == 2 ? cok : (gok && cok));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+using KernelFn = void (*)(CodeDev, const float*, int64_t, int, int, float, const float*, uint8_t*, float*,
+                          int32_t*, uint8_t*);
+
+struct Entry {
+    KernelFn plain, weighted;
+    int wg, fpw;
+};
+
+template <int NL, int RL>
+constexpr Entry make_entry() {
+    return Entry{&bp_kernel<NL, RL, false>, &bp_kernel<NL, RL, true>, Geom<NL, RL>::WG, Geom<NL, RL>::FPW};
+}
+
+// variants: register bits r = 2 or 3 (variant id = r)
+constexpr int kMinN = 3, kMaxN = 12;
+
+const Entry* lookup(int n, int r) {
+    static const Entry table[kMaxN + 1][4] = {
+        {},
+        {},
+        {},
+        {{}, {}, make_entry<3, 2>(), make_entry<3, 3>()},
+        {{}, {}, make_entry<4, 2>(), make_entry<4, 3>()},
+        {{}, {}, make_entry<5, 2>(), make_entry<5, 3>()},
+        {{}, {}, make_entry<6, 2>(), make_entry<6, 3>()},
+        {{}, {}, make_entry<7, 2>(), make_entry<7, 3>()},
+        {{}, {}, make_entry<8, 2>(), make_entry<8, 3>()},
+        {{}, {}, make_entry<9, 2>(), make_entry<9, 3>()},
+        {{}, {}, make_entry<10, 2>(), make_entry<10, 3>()},
+        {{}, {}, make_entry<11, 2>(), make_entry<11, 3>()},
+        {{}, {}, make_entry<12, 2>(), make_entry<12, 3>()},
+    };
+    if (n < kMinN || n > kMaxN || r < 2 || r > 3) return nullptr;
+    return &table[n][r];
+}
+
+}  // namespace bp
+
+bool bp_variant_supported(int n, int variant) { return bp::lookup(n, variant) != nullptr; }
+
+int bp_default_variant(int n) { return n >= 9 ? 3 : 2; }
+
+int bp_list_variants(int n, int32_t* ids, int cap) {
+    int c = 0;
+    for (int r = 2; r <= 3; ++r)
+        if (bp::lookup(n, r)) {
+            if (ids && c < cap) ids[c] = r;
+            ++c;
+        }
+    return c;
+}
+
+polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p, uint8_t* u_hat,
+                       float* llr_u, int32_t* iters, uint8_t* ok, hipStream_t stream) {
+    const int variant = p->variant ? p->variant : bp_default_variant(code->n);
+    const bp::Entry* e = bp::lookup(code->n, variant);
+    if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "bp: no kernel variant for this block length");
+    if (B == 0) return POLAR_OK;
+    const int64_t blocks = (B + e->fpw - 1) / e->fpw;
+    if (blocks > (int64_t)INT32_MAX) return set_error(POLAR_ERR_INVALID_ARG, "bp: batch too large");
+    bp::KernelFn fn = p->weights ? e->weighted : e->plain;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
+                       p->llr_max, p->weights, u_hat, llr_u, iters, ok);
+    return hip_check(hipGetLastError(), "bp_kernel launch");
+}
+
+}  // namespace polarhip
+
+using namespace polarhip;
+
+extern "C" polar_status polar_bp_variants(int32_t N, int32_t* ids, int32_t cap, int32_t* count) {
+    if (!count || cap < 0) return set_error(POLAR_ERR_INVALID_ARG, "polar_bp_variants: bad argument");
+    int n = 0;
+    while ((1 << n) < N) ++n;
+    if ((1 << n) != N) return set_error(POLAR_ERR_INVALID_ARG, "polar_bp_variants: N not a power of two");
+    *count = bp_list_variants(n, ids, cap);
+    return ok_status();
+}
+
+extern "C" polar_status bp_decode_batch(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
+                                        uint8_t* u_hat, float* llr_u, int32_t* iters, uint8_t* ok,
+                                        hipStream_t stream) {
+    if (!code || !p) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: null code or params");
+    if (B < 0) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: negative batch");
+    if (B > 0 && (!llr || !u_hat || !ok)) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: null buffer");
+    if (p->max_iter < 1) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: max_iter must be >= 1");
+    if (p->stop < 0 || p->stop > 2) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: stop must be 0, 1 or 2");
+    if (p->stop == 2 && code->c == 0)
+        return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: CRC stop needs a code with a CRC");
+    if (!(p->llr_max > 0.0f)) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: llr_max must be > 0");
+    if (p->rule != 0) return set_error(POLAR_ERR_UNSUPPORTED, "bp_decode_batch: only the min-sum rule runs on GPU");
+    if (p->weights && p->weight_iters < p->max_iter)
+        return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: weight_iters < max_iter");
+    if (p->variant != 0 && !bp_variant_supported(code->n, p->variant))
+        return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: unknown variant");
+    polar_status st = launch_bp(code, llr, B, p, u_hat, llr_u, iters, ok, stream);
+    return st == POLAR_OK ? ok_status() : st;
+}

@@ -1,0 +1,86 @@
+// internal.hpp -- definitions shared by the host side and the kernels of
+// libpolarhip (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/polar.h"
+
+namespace polarhip {
+
+// Device-side view of a code, passed to kernels by value.
+struct CodeDev {
+    const uint32_t* frozen_bits;  // [max(N/32,1)] bit i of word i/32 set = frozen
+    const int16_t* info_pos;      // [k] non-frozen positions in ascending order
+    const uint32_t* syn;          // [N] CRC syndrome contribution of u_i = 1
+    const uint32_t* syn_nib;      // [N/4][16] syndrome of each nibble value
+    const uint32_t* enc_crc;      // [K] CRC of the unit vector at info bit q
+    int32_t N, n, K, c, k;
+};
+
+}  // namespace polarhip
+
+struct polar_code {
+    int32_t N, n, K, c, k;
+    uint32_t poly;
+    int device;
+    std::vector<uint8_t> frozen;    // host [N]
+    std::vector<int16_t> info_pos;  // host [k]
+    // device allocations (owned)
+    uint32_t* d_frozen_bits = nullptr;
+    int16_t* d_info_pos = nullptr;
+    uint32_t* d_syn = nullptr;
+    uint32_t* d_syn_nib = nullptr;
+    uint32_t* d_enc_crc = nullptr;
+    polarhip::CodeDev dev() const {
+        polarhip::CodeDev d;
+        d.frozen_bits = d_frozen_bits;
+        d.info_pos = d_info_pos;
+        d.syn = d_syn;
+        d.syn_nib = d_syn_nib;
+        d.enc_crc = d_enc_crc;
+        d.N = N;
+        d.n = n;
+        d.K = K;
+        d.c = c;
+        d.k = k;
+        return d;
+    }
+};
+
+namespace polarhip {
+
+// error reporting (thread local)
+polar_status set_error(polar_status st, const std::string& msg);
+polar_status ok_status();
+polar_status hip_check(hipError_t e, const char* what);
+
+// launch helpers implemented in the kernel translation units
+polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
+                       uint8_t* u_hat, float* llr_u, int32_t* iters, uint8_t* ok,
+                       hipStream_t stream);
+bool bp_variant_supported(int n, int variant);
+int bp_default_variant(int n);
+int bp_list_variants(int n, int32_t* ids, int cap);
+
+struct SclPlan {
+    int gl;            // levels >= gl live in global memory
+    size_t lds_bytes;  // dynamic LDS per workgroup
+    size_t glob_per_wg;  // global bytes per workgroup (levels >= gl, LLRs and partial sums)
+    int grid;          // workgroups launched
+};
+polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan);
+polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,
+                        const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host,
+                        uint8_t* u_hat, uint8_t* crc_ok, float* pm, void* glob,
+                        hipStream_t stream);
+
+int device_cu_count();
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace polarhip
