@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "libpolarhip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-COMMON = ["-O3", "-std=c++20", "-fPIC", "-ffp-contract=off", f"-I{os.path.join(ROOT, 'include')}"]
-DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-std=c++20", "-fPIC", "-ffp-contract=off", "-fno-honor-nans", f"-I{os.path.join(ROOT, 'include')}"]
+DEVICE = [f"--offload-arch={ARCH}", "-mno-amdgpu-ieee", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def sources():

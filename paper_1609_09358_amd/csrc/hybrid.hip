@@ -27,26 +27,52 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict_
     if (fail) queue[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)f;
 }
 
-// info_hat <- information bits of u_hat (BP result or its SCL replacement)
+// info_hat <- information bits of u_hat (BP result or its SCL replacement);
+// 32 frames per workgroup, statistics reduced per wavefront before the atomics
+constexpr int kMergeFrames = 32;
+
 __global__ __launch_bounds__(256) void merge_kernel(CodeDev code, const uint8_t* __restrict__ u_hat,
                                                     const uint8_t* __restrict__ ok,
                                                     const int32_t* __restrict__ iters,
                                                     const uint8_t* __restrict__ scl_ok, int64_t B,
                                                     uint8_t* __restrict__ info_hat, uint8_t* __restrict__ used_scl,
                                                     unsigned long long* __restrict__ stats) {
-    const int64_t f = blockIdx.x;
     const int K = code.K, N = code.N;
-    const uint8_t* u = u_hat + f * N;
-    for (int q = threadIdx.x; q < K; q += blockDim.x) info_hat[f * K + q] = u[code.info_pos[q]];
-    if (threadIdx.x == 0) {
-        const bool good = ok[f] != 0;
-        if (used_scl) used_scl[f] = good ? 0 : 1;
+    const int64_t f0 = (int64_t)blockIdx.x * kMergeFrames;
+    const int nf = (int)((B - f0) < kMergeFrames ? (B - f0) : kMergeFrames);
+    for (int it = threadIdx.x; it < nf * K; it += blockDim.x) {
+        const int lf = it / K, q = it - lf * K;
+        const int64_t f = f0 + lf;
+        info_hat[f * K + q] = u_hat[f * N + code.info_pos[q]];
+    }
+    if (threadIdx.x < 64) {
+        const int lf = threadIdx.x;
+        unsigned long long s_bp = 0, s_scl = 0, s_it = 0, s_fail = 0, s_n = 0;
+        if (lf < nf) {
+            const int64_t f = f0 + lf;
+            const bool good = ok[f] != 0;
+            if (used_scl) used_scl[f] = good ? 0 : 1;
+            s_n = 1;
+            s_bp = good;
+            s_scl = !good;
+            s_it = (unsigned long long)iters[f];
+            s_fail = (!good && !scl_ok[f]) ? 1ull : 0ull;
+        }
         if (stats) {
-            atomicAdd(&stats[0], 1ull);
-            if (good) atomicAdd(&stats[1], 1ull);
-            else atomicAdd(&stats[2], 1ull);
-            atomicAdd(&stats[3], (unsigned long long)iters[f]);
-            if (!good && !scl_ok[f]) atomicAdd(&stats[4], 1ull);
+            for (int m = 32; m >= 1; m >>= 1) {
+                s_n += __shfl_xor(s_n, m, 64);
+                s_bp += __shfl_xor(s_bp, m, 64);
+                s_scl += __shfl_xor(s_scl, m, 64);
+                s_it += __shfl_xor(s_it, m, 64);
+                s_fail += __shfl_xor(s_fail, m, 64);
+            }
+            if (lf == 0) {
+                atomicAdd(&stats[0], s_n);
+                if (s_bp) atomicAdd(&stats[1], s_bp);
+                if (s_scl) atomicAdd(&stats[2], s_scl);
+                atomicAdd(&stats[3], s_it);
+                if (s_fail) atomicAdd(&stats[4], s_fail);
+            }
         }
     }
 }
@@ -144,7 +170,7 @@ extern "C" polar_status hybrid_decode_batch(const polar_code* code, const float*
     if ((st = launch_scl(code, plan, llr, L, w.queue, w.count, 0, w.u_hat, w.scl_ok, nullptr, w.scl_glob, stream)) !=
         POLAR_OK)
         return st;
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)B), dim3(64), 0, stream, code->dev(), w.u_hat, w.ok, w.iters,
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((B + kMergeFrames - 1) / kMergeFrames)), dim3(256), 0, stream, code->dev(), w.u_hat, w.ok, w.iters,
                        w.scl_ok, B, info_hat, used_scl, reinterpret_cast<unsigned long long*>(stats));
     if ((st = hip_check(hipGetLastError(), "merge launch")) != POLAR_OK) return st;
     return ok_status();

@@ -1,23 +1,34 @@
 // scl.hip -- CRC-aided successive-cancellation list decoder (Sec. II-A).
 //
 // One wavefront decodes one frame at a time; workgroups stay resident and walk
-// a list of frames (a device-side count, so the hybrid decoder can feed it the
-// compacted BP failures without a host round trip).
+// a list of frames whose length may live on the device (the hybrid decoder
+// feeds it the compacted BP failures without a host round trip).
 //
-// Per path slot the wavefront keeps the LLR tree (level d holds 2^d values,
-// level n is the channel) and the partial sums.  Paths are copied lazily: each
-// slot keeps, per level, the slot whose array it reads.  Bit i rewrites
-// levels ctz(i)..0 of every path into the path's own slot and reads level
-// ctz(i)+1 through the pointer, which no path writes during bit i; partial
-// sums are handled the same way.  A branching path therefore copies only its
-// pointer vector.  Survivors are chosen by rank among the 2L candidates under
-// the order (metric, parent list position, bit) -- the pruned pseudo sort of
-// Sec. II-A with a strict tie rule -- and a survivor's new slot is its rank,
-// so slot index and list position coincide.  The CRC is tracked per path as a
+// Path slot l is owned by lane l.  The LLR tree of a path (level d holds 2^d
+// values, level n is the channel) and its partial sums (level d holds 2^d
+// bits) are split in two:
+//   - levels below BL = min(n, 5) live in the registers of the owning lane;
+//   - levels BL and above live in LDS (the largest ones optionally in a global
+//     slice) and are shared lazily: each slot keeps, per level, the slot whose
+//     array it reads.  Bit i rewrites levels ctz(i)..BL of every path into the
+//     path's own slot and reads level ctz(i)+1 through the pointer, which no
+//     path writes during bit i; partial sums are handled the same way.
+// Bits are processed in blocks of 2^BL.  Inside a block, ctz(i) and the number
+// of trailing ones of i are compile-time constants, so a block is unrolled
+// into straight-line code: a bit recomputes levels ctz(i)..0 in registers
+// (level BL is read from LDS at the block start and once in the middle),
+// decides, and folds the decided bit into the partial sums held in registers.
+// A branching path is copied by pulling from the parent's lane exactly the
+// registers that later bits of the block still read, plus the two pointer
+// vectors.  Survivors are chosen by rank among the 2L candidates under the
+// order (metric, parent list position, bit) -- the pruned pseudo sort of
+// Sec. II-A with a strict tie rule -- and a survivor's slot is its rank, so
+// slot index and list position coincide.  The CRC is tracked per path as a
 // running syndrome (linear in the decided bits); the decoded bits of the
 // chosen path are recovered from a per-information-bit trace of
-// (parent, bit).  Small levels live in LDS; the largest levels can be placed
-// in a per-workgroup global slice to raise the number of resident frames.
+// (parent, bit).
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace polarhip {
@@ -41,180 +52,295 @@ __device__ __forceinline__ void wg_mem_order() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-struct Layout {
-    int gl;   // levels < gl in LDS
-    int sl;   // LDS stride of one slot's LLR levels (floats)
-    int psl;  // LDS stride of one slot's partial sums (bytes)
+// 16 one-byte entries (slot read at each level) held in two 64-bit registers
+struct PtrVec {
+    uint64_t lo, hi;
 };
 
-template <int L>
+__device__ __forceinline__ int get_byte(const PtrVec& v, int idx) {
+    const uint64_t w = idx < 8 ? v.lo : v.hi;
+    return (int)((w >> (8 * (idx & 7))) & 0xFFull);
+}
+
+__device__ __forceinline__ void set_byte(PtrVec& v, int idx, int val) {
+    const int sh = 8 * (idx & 7);
+    const uint64_t m = ~(0xFFull << sh);
+    const uint64_t add = (uint64_t)val << sh;
+    if (idx < 8) v.lo = (v.lo & m) | add;
+    else v.hi = (v.hi & m) | add;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    return (uint64_t)__shfl((unsigned long long)v, src, 64);
+}
+
+// word offset of partial-sum level d >= 5 inside a slot's LDS words
+__device__ __forceinline__ int ps_off(int d) { return (1 << (d - 5)) - 1; }
+
+constexpr int ctz_c(int v) {
+    int c = 0;
+    while (((v >> c) & 1) == 0) ++c;
+    return c;
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// partial-sum block of 2^T bits finished by `bit`, from the T levels below it
+template <int T>
+__device__ __forceinline__ uint32_t combine(uint32_t bit, const uint32_t (&ps)[5]) {
+    uint32_t cur = bit;
+#pragma unroll
+    for (int d = 0; d < T; ++d) {
+        const uint32_t h = 1u << d;
+        const uint32_t lowmask = (h >= 32u) ? 0xFFFFFFFFu : ((1u << h) - 1u);
+        cur = ((ps[d] ^ cur) & lowmask) | (cur << h);
+    }
+    return cur;
+}
+
+// rank of this lane's candidate among the first ncand lanes under
+// (metric, lane); metrics are non-negative, so their bit patterns order them
+__device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float met, int lane) {
+    if (lane < ncand) mets[lane] = __float_as_uint(met);
+    wave_mem_order();
+    const uint32_t mb = __float_as_uint(met);
+    int rank = 0;
+    for (int c4 = 0; c4 < ncand; c4 += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(mets + c4);
+        rank += (v.x < mb || (v.x == mb && c4 + 0 < lane)) ? 1 : 0;
+        rank += (c4 + 1 < ncand && (v.y < mb || (v.y == mb && c4 + 1 < lane))) ? 1 : 0;
+        rank += (c4 + 2 < ncand && (v.z < mb || (v.z == mb && c4 + 2 < lane))) ? 1 : 0;
+        rank += (c4 + 3 < ncand && (v.w < mb || (v.w == mb && c4 + 3 < lane))) ? 1 : 0;
+    }
+    return rank;
+}
+
+struct Layout {
+    int gl;   // LLR levels < gl in LDS, the others in the workgroup's global slice
+    int sl;   // LDS floats per slot (LLR heap, padded)
+    int pw;   // partial-sum words per slot (levels >= 5)
+};
+
+template <int L, int BL>
 __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
                                                  uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                                                  float* __restrict__ pm_out, float* __restrict__ glam_all,
-                                                 uint8_t* __restrict__ gps_all, Layout lay) {
+                                                 Layout lay) {
+    constexpr int BS = 1 << BL;  // bits per block
     extern __shared__ __attribute__((aligned(16))) unsigned char sm[];
     const int lane = threadIdx.x;
-    const int n = code.n, N = code.N, k = code.k;
-    const int gl = lay.gl, SL = lay.sl, PSL = lay.psl;
+    const int n = code.n, N = code.N;
+    const int gl = lay.gl, SL = lay.sl, PW = lay.pw;
 
-    float* slam = reinterpret_cast<float*>(sm);                                  // [L][SL]
-    float* scr_pm = slam + L * SL;                                               // [L]
-    uint32_t* scr_syn = reinterpret_cast<uint32_t*>(scr_pm + L);                 // [L]
-    uint8_t* sps = reinterpret_cast<uint8_t*>(scr_syn + L);                      // [L][PSL]
-    uint8_t* ptrA = sps + L * PSL;                                               // [2][L][16] LLR level pointers
-    uint8_t* ptrB = ptrA + 2 * L * 16;                                           // [2][L][16] partial-sum pointers
-    uint8_t* scr_par = ptrB + 2 * L * 16;                                        // [L]
-    uint8_t* scr_bit = scr_par + L;                                              // [L]
-    uint8_t* dec = scr_bit + L;                                                  // [N]
-    uint8_t* tbk = dec + N;                                                      // [k][L]
+    float* slam = reinterpret_cast<float*>(sm);                   // [L][SL]
+    uint32_t* psw = reinterpret_cast<uint32_t*>(slam + L * SL);   // [L][PW]
+    uint32_t* mets = psw + L * PW;                                // [64]
+    int32_t* inv = reinterpret_cast<int32_t*>(mets + 64);         // [L]
+    uint8_t* tbk = reinterpret_cast<uint8_t*>(inv + L);           // [k][L]
+    uint8_t* dec = reinterpret_cast<uint8_t*>(slam);              // [N], reuses the LLR area at the end
 
     float* glam = glam_all ? glam_all + (size_t)blockIdx.x * L * N : nullptr;
-    uint8_t* gps = gps_all ? gps_all + (size_t)blockIdx.x * L * N : nullptr;
-
-    auto lam_rd = [&](int slot, int d, int e) -> float {
-        return d < gl ? slam[slot * SL + (1 << d) + e] : glam[(size_t)slot * N + (1 << d) + e];
-    };
-    auto lam_wr = [&](int slot, int d, int e, float v) {
-        if (d < gl) slam[slot * SL + (1 << d) + e] = v;
-        else glam[(size_t)slot * N + (1 << d) + e] = v;
-    };
-    auto ps_rd = [&](int slot, int d, int e) -> uint8_t {
-        return d < gl ? sps[slot * PSL + (1 << d) + e] : gps[(size_t)slot * N + (1 << d) + e];
-    };
-    auto ps_wr = [&](int slot, int d, int e, uint8_t v) {
-        if (d < gl) sps[slot * PSL + (1 << d) + e] = v;
-        else gps[(size_t)slot * N + (1 << d) + e] = v;
-    };
-    auto order = [&](int d) {
-        if (d < gl) wave_mem_order(); else wg_mem_order();
-    };
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
     for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
         const int64_t f = frame_ids ? (int64_t)frame_ids[q] : q;
         const float* chan = llr + f * N;
 
-        // initial list: one path in slot 0, all pointers to slot 0
-        for (int it = lane; it < 2 * 2 * L * 16; it += 64) ptrA[it] = 0;  // ptrA and ptrB are contiguous
-        for (int it = lane; it < N; it += 64) dec[it] = 0;
         int act = 1;
-        int cur = 0;
         float PM = 0.0f;
         uint32_t SYN = 0u;
+        PtrVec ptrL{0ull, 0ull};  // slot read at each LLR level >= BL
+        PtrVec ptrP{0ull, 0ull};  // slot read at each partial-sum level >= 5
+        float lv[32];             // levels 0..BL-1, heap order: level d at [2^d, 2^(d+1))
+        uint32_t ps[5];           // partial-sum levels 0..BL-1: bit e of word d
+#pragma unroll
+        for (int e = 0; e < 32; ++e) lv[e] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) ps[d] = 0u;
         int infoq = 0;
-        wave_mem_order();
 
-        for (int i = 0; i < N; ++i) {
-            const int top = (i == 0) ? n - 1 : __builtin_ctz((unsigned)i);
-            float lam_own = 0.0f;
-            // ---- LLR levels top..0
-            for (int d = top; d >= 0; --d) {
-                const int sz = 1 << d;
-                const int items = act << d;
-                for (int it = lane; it < items; it += 64) {
-                    const int slot = it >> d;
-                    const int e = it & (sz - 1);
-                    float a, b;
-                    if (d + 1 == n) {
-                        a = chan[e];
-                        b = chan[e + sz];
-                    } else {
-                        const int src = (d == top) ? ptrA[(cur * L + slot) * 16 + d + 1] : slot;
-                        a = lam_rd(src, d + 1, e);
-                        b = lam_rd(src, d + 1, e + sz);
-                    }
-                    float val;
-                    if (d == top && i != 0) {
-                        const int ps_src = ptrB[(cur * L + slot) * 16 + d];
-                        val = ps_rd(ps_src, d, e) ? b - a : b + a;
-                    } else {
-                        val = g_ms(a, b);
-                    }
-                    lam_wr(slot, d, e, val);
-                    if (d == 0) lam_own = val;
-                }
-                order(d);
-            }
-            // levels 0..top are now owned by every path
-            for (int it = lane; it < act * (top + 1); it += 64) {
-                const int slot = it / (top + 1), d = it % (top + 1);
-                ptrA[(cur * L + slot) * 16 + d] = (uint8_t)slot;
-            }
-            // ---- decision
-            int bit = 0;
-            const bool frozen = (code.frozen_bits[i >> 5] >> (i & 31)) & 1u;
-            if (frozen) {
-                if (lane < act) {
-                    const float pen = lam_own < 0.0f ? fabsf(lam_own) : 0.0f;
-                    PM = PM + pen;
-                }
-            } else {
-                const int ncand = 2 * act;
-                const int p = lane >> 1, b = lane & 1;
-                const float lp = __shfl(lam_own, p, 64);
-                const float pmp = __shfl(PM, p, 64);
-                const uint32_t sp = __shfl(SYN, p, 64);
-                const bool hd = lp < 0.0f;
-                const float pen = (b != (int)hd) ? fabsf(lp) : 0.0f;
-                const float met = pmp + pen;
-                int rank = 0;
-                for (int c2 = 0; c2 < ncand; ++c2) {
-                    const float m2 = __shfl(met, c2, 64);
-                    rank += (m2 < met || (m2 == met && c2 < lane)) ? 1 : 0;
-                }
-                const int nact = ncand < L ? ncand : L;
-                const uint32_t syn_i = code.syn[i];
-                if (lane < ncand && rank < L) {
-                    scr_pm[rank] = met;
-                    scr_syn[rank] = sp ^ (b ? syn_i : 0u);
-                    scr_par[rank] = (uint8_t)p;
-                    scr_bit[rank] = (uint8_t)b;
-                }
-                wave_mem_order();
-                int par = 0;
-                if (lane < nact) {
-                    PM = scr_pm[lane];
-                    SYN = scr_syn[lane];
-                    par = scr_par[lane];
-                    bit = scr_bit[lane];
-                    tbk[infoq * L + lane] = (uint8_t)(par | (bit << 7));
-                }
-                const int nxt = cur ^ 1;
-                for (int it = lane; it < nact * 16; it += 64) {
-                    const int slot = it >> 4, d = it & 15;
-                    const int ps = scr_par[slot];
-                    ptrA[(nxt * L + slot) * 16 + d] = ptrA[(cur * L + ps) * 16 + d];
-                    ptrB[(nxt * L + slot) * 16 + d] = ptrB[(cur * L + ps) * 16 + d];
-                }
-                wave_mem_order();
-                cur = nxt;
-                act = nact;
-                ++infoq;
-            }
-            // ---- partial sums: finished sub-block of size 2^t goes to level t
-            const int t = __builtin_ctz(~(unsigned)i);
-            if (t < n) {
-                const int base = (1 << t);
-                if (lane < act) ps_wr(lane, t, base - 1, (uint8_t)bit);
-                order(t);
-                for (int d = 0; d < t; ++d) {
+        for (int j = 0; j < (N >> BL); ++j) {
+            const int i0 = j << BL;
+            const uint32_t fw = (code.frozen_bits[i0 >> 5] >> (i0 & 31)) & (BS == 32 ? 0xFFFFFFFFu : ((1u << BS) - 1u));
+            // ---------------- block start: levels top..BL, all lanes together
+            if (BL < n) {
+                const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
+                for (int d = top; d >= BL; --d) {
                     const int sz = 1 << d;
                     const int items = act << d;
+                    const int myp = get_byte(ptrL, d + 1);
+                    const int mypp = get_byte(ptrP, d);
                     for (int it = lane; it < items; it += 64) {
-                        const int slot = it >> d, e = it & (sz - 1);
-                        const int src = ptrB[(cur * L + slot) * 16 + d];
-                        const uint8_t v = ps_rd(src, d, e) ^ ps_rd(slot, t, base - sz + e);
-                        ps_wr(slot, t, base - 2 * sz + e, v);
+                        const int slot = it >> d;
+                        const int e = it & (sz - 1);
+                        float a, b;
+                        if (d + 1 == n) {
+                            a = chan[e];
+                            b = chan[e + sz];
+                        } else {
+                            const int src = (d == top) ? __shfl(myp, slot, 64) : slot;
+                            if (d + 1 < gl) {
+                                const float* p = slam + src * SL + (2 << d);
+                                a = p[e];
+                                b = p[e + sz];
+                            } else {
+                                const float* p = glam + (size_t)src * N + (2 << d);
+                                a = p[e];
+                                b = p[e + sz];
+                            }
+                        }
+                        float val;
+                        if (d == top && j != 0) {
+                            const int pss = __shfl(mypp, slot, 64);
+                            const uint32_t w = psw[pss * PW + ps_off(d) + (e >> 5)];
+                            val = ((w >> (e & 31)) & 1u) ? b - a : b + a;
+                        } else {
+                            val = g_ms(a, b);
+                        }
+                        if (d < gl) slam[slot * SL + sz + e] = val;
+                        else glam[(size_t)slot * N + sz + e] = val;
                     }
-                    order(t);
+                    if (d < gl) wave_mem_order(); else wg_mem_order();
+                    if (lane < act) set_byte(ptrL, d, lane);
                 }
-                if (lane < act) ptrB[(cur * L + lane) * 16 + t] = (uint8_t)lane;
-                wave_mem_order();
             }
+            // ---------------- the 2^BL bits of the block, unrolled
+            static_for<0, BS>([&](auto RC) {
+                constexpr int r = decltype(RC)::value;
+                // lowest level whose index bit changed at this bit (BL: block start)
+                constexpr int top = (r == 0) ? BL : ctz_c(r);
+                // levels still read by later bits of this block after bit r
+                constexpr int live_from = (r + 1 < BS) ? (2 << ctz_c(r + 1)) : 32;
+                // trailing ones of the bit index (>= BL at the block's last bit)
+                constexpr int tb = (r + 1 < BS) ? ctz_c(~r) : BL;
+                const int i = i0 + r;
+
+                // ---- LLR levels min(top, BL-1)..0 of this lane's path
+                if (lane < act) {
+                    float src[32];
+                    constexpr int sl_lv = (r == 0) ? BL : top + 1;  // level read
+                    if constexpr (sl_lv == BL) {
+                        if (BL == n) {
+#pragma unroll
+                            for (int e = 0; e < BS; ++e) src[e] = chan[e];
+                        } else {
+                            const int sl = (r == 0) ? lane : get_byte(ptrL, BL);
+                            const float* p = slam + sl * SL + BS;
+#pragma unroll
+                            for (int e4 = 0; e4 < BS / 4; ++e4) {
+                                const float4 t4 = reinterpret_cast<const float4*>(p)[e4];
+                                src[4 * e4] = t4.x;
+                                src[4 * e4 + 1] = t4.y;
+                                src[4 * e4 + 2] = t4.z;
+                                src[4 * e4 + 3] = t4.w;
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < (1 << sl_lv); ++e) src[e] = lv[(1 << sl_lv) + e];
+                    }
+                    constexpr int dhi = sl_lv - 1;  // first level computed here
+#pragma unroll
+                    for (int d = dhi; d >= 0; --d) {
+#pragma unroll
+                        for (int e = 0; e < (1 << d); ++e) {
+                            const float a = (d == dhi) ? src[e] : lv[(2 << d) + e];
+                            const float b = (d == dhi) ? src[e + (1 << d)] : lv[(2 << d) + e + (1 << d)];
+                            if (r != 0 && d == top)
+                                lv[(1 << d) + e] = ((ps[d] >> e) & 1u) ? b - a : b + a;
+                            else
+                                lv[(1 << d) + e] = g_ms(a, b);
+                        }
+                    }
+                }
+                const float lam0 = lv[1];
+                // ---- decision
+                uint32_t bit = 0;
+                if ((fw >> r) & 1u) {
+                    if (lane < act) PM = PM + (lam0 < 0.0f ? fabsf(lam0) : 0.0f);
+                } else {
+                    const int ncand = 2 * act;
+                    const int p = lane >> 1, b = lane & 1;
+                    const float lp = __shfl(lam0, p, 64);
+                    const float pmp = __shfl(PM, p, 64);
+                    const float pen = (b != (lp < 0.0f ? 1 : 0)) ? fabsf(lp) : 0.0f;
+                    const float met = pmp + pen;
+                    const int rank = candidate_rank(mets, ncand, met, lane);
+                    const int nact = ncand < L ? ncand : L;
+                    if (lane < ncand && rank < L) inv[rank] = lane;
+                    wave_mem_order();
+                    const int c = lane < nact ? inv[lane] : 0;
+                    const int par = c >> 1;
+                    const uint32_t cb = (uint32_t)(c & 1);
+                    const uint32_t syn_i = code.syn[i];
+                    // pull the parent's state: metric, syndrome, pointers, live registers
+                    const float nm = __shfl(met, c, 64);
+                    const uint32_t ns = __shfl(SYN, par, 64) ^ (cb ? syn_i : 0u);
+                    PtrVec nL, nP;
+                    nL.lo = shfl64(ptrL.lo, par);
+                    nL.hi = shfl64(ptrL.hi, par);
+                    nP.lo = shfl64(ptrP.lo, par);
+                    nP.hi = shfl64(ptrP.hi, par);
+                    uint32_t nps[5];
+#pragma unroll
+                    for (int d = 0; d < BL; ++d) nps[d] = __shfl(ps[d], par, 64);
+                    float nlv[32];
+#pragma unroll
+                    for (int e = live_from; e < BS; ++e) nlv[e] = __shfl(lv[e], par, 64);
+                    if (lane < nact) {
+                        PM = nm;
+                        SYN = ns;
+                        ptrL = nL;
+                        ptrP = nP;
+#pragma unroll
+                        for (int d = 0; d < BL; ++d) ps[d] = nps[d];
+#pragma unroll
+                        for (int e = live_from; e < BS; ++e) lv[e] = nlv[e];
+                        bit = cb;
+                        tbk[infoq * L + lane] = (uint8_t)(par | (cb << 7));
+                    }
+                    act = nact;
+                    ++infoq;
+                }
+                // ---- partial sums: the finished block of 2^t bits becomes level t
+                if constexpr (tb < BL) {
+                    if (lane < act) ps[tb] = combine<tb>(bit, ps);
+                } else {
+                    const int t = (BL == n) ? n : BL + __builtin_ctz(~(unsigned)j);
+                    if (t < n) {
+                        // level t >= 5 lives in LDS: W = 2^(t-5) words built in place
+                        // from the end, starting with this 32-bit block
+                        const int W = 1 << (t - 5);
+                        const int ot = ps_off(t);
+                        if (lane < act) psw[lane * PW + ot + W - 1] = combine<BL>(bit, ps);
+                        wave_mem_order();
+                        for (int d = 5; d < t; ++d) {
+                            const int sz = 1 << (d - 5);
+                            const int items = act * sz;
+                            const int mypp = get_byte(ptrP, d);
+                            for (int it = lane; it < items; it += 64) {
+                                const int slot = it >> (d - 5), w = it & (sz - 1);
+                                const int pss = __shfl(mypp, slot, 64);
+                                const uint32_t v = psw[pss * PW + ps_off(d) + w] ^ psw[slot * PW + ot + W - sz + w];
+                                psw[slot * PW + ot + W - 2 * sz + w] = v;
+                            }
+                            wave_mem_order();
+                        }
+                        if (lane < act) set_byte(ptrP, t, lane);
+                        wave_mem_order();
+                    }
+                }
+            });
         }
-        // ---- selection: smallest (CRC fails, metric, position)
+        // ---------------- selection: smallest (CRC fails, metric, position)
         uint64_t key = ~0ull;
         if (lane < act)
             key = ((uint64_t)(SYN != 0u) << 40) | ((uint64_t)__float_as_uint(PM) << 8) | (uint64_t)lane;
@@ -225,7 +351,10 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
         const int best = (int)(key & 0xFF);
         const bool best_ok = ((key >> 40) & 1ull) == 0;
         const float best_pm = __shfl(PM, best, 64);
-        // ---- trace back the chosen path through the information bits
+        wave_mem_order();
+        for (int it = lane; it < N; it += 64) dec[it] = 0;
+        wave_mem_order();
+        // ---------------- trace the chosen path back through the information bits
         if (lane == 0) {
             int s = best;
             for (int qq = infoq - 1; qq >= 0; --qq) {
@@ -245,45 +374,57 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
 }
 
 using KernelFn = void (*)(CodeDev, const float*, const int32_t*, const int32_t*, int64_t, uint8_t*, uint8_t*,
-                          float*, float*, uint8_t*, Layout);
+                          float*, float*, Layout);
 
-KernelFn pick(int L) {
-    switch (L) {
-        case 1: return &scl_kernel<1>;
-        case 2: return &scl_kernel<2>;
-        case 4: return &scl_kernel<4>;
-        case 8: return &scl_kernel<8>;
-        case 16: return &scl_kernel<16>;
-        case 32: return &scl_kernel<32>;
+template <int L>
+KernelFn pick_bl(int bl) {
+    switch (bl) {
+        case 3: return &scl_kernel<L, 3>;
+        case 4: return &scl_kernel<L, 4>;
+        case 5: return &scl_kernel<L, 5>;
         default: return nullptr;
     }
 }
 
-size_t lds_bytes(int L, int N, int k, int gl) {
-    const size_t sl = (size_t(1) << gl) + 1;
-    const size_t psl = (size_t(1) << gl);
+KernelFn pick(int L, int n) {
+    const int bl = n < 5 ? n : 5;
+    switch (L) {
+        case 1: return pick_bl<1>(bl);
+        case 2: return pick_bl<2>(bl);
+        case 4: return pick_bl<4>(bl);
+        case 8: return pick_bl<8>(bl);
+        case 16: return pick_bl<16>(bl);
+        case 32: return pick_bl<32>(bl);
+        default: return nullptr;
+    }
+}
+
+int ps_words(int n) { return n <= 5 ? 1 : (1 << (n - 5)) - 1; }
+
+size_t lds_bytes(int L, int N, int n, int k, int gl) {
+    const size_t sl = (size_t(1) << gl) + 4;
     size_t b = 0;
-    b += (size_t)L * sl * 4;   // LLR levels
-    b += (size_t)L * 4 * 2;    // scratch metric + syndrome
-    b += (size_t)L * psl;      // partial sums
-    b += (size_t)2 * L * 16 * 2;  // pointer vectors
-    b += (size_t)L * 2;        // scratch parent + bit
-    b += (size_t)N;            // decoded bits
-    b += (size_t)k * L;        // trace
+    b += (size_t)L * sl * 4;           // LLR heap (levels BL..gl-1 used)
+    b += (size_t)L * ps_words(n) * 4;  // partial sums of levels >= 5
+    b += 64 * 4;                       // candidate metrics
+    b += (size_t)L * 4;                // inverse permutation
+    b += (size_t)k * L;                // trace
+    b = b > (size_t)N ? b : (size_t)N;  // the decoded bits reuse the space
     return align_up(b, 16);
 }
 
 }  // namespace scl
 
-static size_t g_scl_lds_budget = 48 * 1024;
+static size_t g_scl_lds_budget = 40 * 1024;
 
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan) {
-    scl::KernelFn fn = scl::pick(L);
-    if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
     const int n = code->n, N = code->N, k = code->k;
+    scl::KernelFn fn = scl::pick(L, n);
+    if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
+    const int gl_min = n < 6 ? n : 6;
     int gl = n;
-    while (gl > 1 && scl::lds_bytes(L, N, k, gl) > g_scl_lds_budget) --gl;
-    size_t lds = scl::lds_bytes(L, N, k, gl);
+    while (gl > gl_min && scl::lds_bytes(L, N, n, k, gl) > g_scl_lds_budget) --gl;
+    size_t lds = scl::lds_bytes(L, N, n, k, gl);
     if (lds > 160 * 1024) return set_error(POLAR_ERR_UNSUPPORTED, "scl: list too large for LDS");
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds);
@@ -293,7 +434,7 @@ polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan
     if (grid < 1) grid = 1;
     plan->gl = gl;
     plan->lds_bytes = lds;
-    plan->glob_per_wg = (gl < n) ? (size_t)L * N * 5 : 0;
+    plan->glob_per_wg = (gl < n) ? (size_t)L * N * 4 : 0;
     plan->grid = (int)grid;
     return POLAR_OK;
 }
@@ -301,19 +442,14 @@ polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host, uint8_t* u_hat,
                         uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream) {
-    scl::KernelFn fn = scl::pick(L);
-    float* glam = nullptr;
-    uint8_t* gps = nullptr;
-    if (plan.glob_per_wg) {
-        glam = reinterpret_cast<float*>(glob);
-        gps = reinterpret_cast<uint8_t*>(glam + (size_t)plan.grid * L * code->N);
-    }
+    scl::KernelFn fn = scl::pick(L, code->n);
     scl::Layout lay;
     lay.gl = plan.gl;
-    lay.sl = (1 << plan.gl) + 1;
-    lay.psl = 1 << plan.gl;
+    lay.sl = (1 << plan.gl) + 4;
+    lay.pw = scl::ps_words(code->n);
+    float* glam = plan.glob_per_wg ? reinterpret_cast<float*>(glob) : nullptr;
     hipLaunchKernelGGL(fn, dim3(plan.grid), dim3(64), plan.lds_bytes, stream, code->dev(), llr, frame_ids,
-                       count_dev, count_host, u_hat, crc_ok, pm, glam, gps, lay);
+                       count_dev, count_host, u_hat, crc_ok, pm, glam, lay);
     return hip_check(hipGetLastError(), "scl_kernel launch");
 }
 
