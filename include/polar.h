@@ -196,6 +196,42 @@ polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64
 polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,
                                   const bp_params* params, size_t* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Weighted (learned) min-sum BP -- not in the paper; trains the weights of the
+ * weighted form of bp_decode_batch.  W: dev float [T][2][n][N] as in bp_params.
+ * ------------------------------------------------------------------------- */
+
+/* T weighted iterations, no early stop.  llr_u dev [B][N] (soft output
+ * LLR(u) = L_{i,1} + R_{i,1}), u_hat dev [B][N] (hard decisions), saved dev
+ * [B][T][2][n][N] or NULL: every message produced, saved[f][t][d][s][i] = the
+ * row of direction d (0 = R, row s+1; 1 = L, row s) that column s produced in
+ * iteration t -- the input of wbp_backward. */
+polar_status wbp_forward(const polar_code* code, const float* llr, int64_t B, const float* W, int32_t T,
+                         float llr_max, int32_t variant, float* llr_u, uint8_t* u_hat, float* saved,
+                         hipStream_t stream);
+
+/* Binary cross-entropy of P(u_i = 1) = sigmoid(-llr_u_i) against u_true (dev
+ * [B][N] bits) over the non-frozen positions: loss dev [B] or NULL (per frame,
+ * times scale), dlam dev [B][N] = scale * d(loss)/d(llr_u) (0 on frozen
+ * positions).  Computed in double precision, stored as float. */
+polar_status wbp_bce(const polar_code* code, const float* llr_u, const uint8_t* u_true, int64_t B, double scale,
+                     float* loss, float* dlam, hipStream_t stream);
+
+/* Reverse-mode gradient of the weighted BP: dW dev [T][2][n][N] = sum over the
+ * B frames (in frame order, accumulated in double) of d(loss)/dW given dlam =
+ * d(loss)/d(llr_u) dev [B][N]; dllr dev [B][N] or NULL = d(loss)/d(llr).
+ * `saved` (from wbp_forward with the same llr, W, T) is used as scratch and is
+ * undefined afterwards.  Deterministic. */
+polar_status wbp_backward(const polar_code* code, const float* llr, int64_t B, const float* W, int32_t T,
+                          float llr_max, int32_t variant, float* saved, const float* dlam, float* dW, float* dllr,
+                          hipStream_t stream);
+
+/* One Adam step (Kingma and Ba, 2015) on `count` float parameters, step >= 1:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr m_hat / (sqrt(v_hat) + eps)
+ * with bias corrections 1 - b^step.  All arrays dev, updated in place. */
+polar_status polar_adam_step(float* w, const float* g, float* m, float* v, int64_t count, int32_t step, float lr,
+                             float beta1, float beta2, float eps, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

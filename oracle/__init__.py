@@ -55,6 +55,8 @@ def _lib(prec: str = "f64"):
         lib.orc_wbp_grad_batch.restype = C.c_double
         lib.orc_wbp_grad_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int,
                                            C.c_double, _f64p, C.c_double, _f64p, _f64p]
+        lib.orc_wbp_backward_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, C.c_int, C.c_double, _f64p,
+                                               _f64p, _f64p, _f64p]
         lib.orc_adam_step.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_double]
         _LIBS[prec] = lib
@@ -285,6 +287,23 @@ def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", wa
     if want_dllr:
         return loss, dW, dl
     return loss, dW
+
+
+def wbp_backward(llr, frozen, T, W, dlam, llr_max=20.0, prec="f64"):
+    """Adjoint of the weighted BP for a given d loss / d lambda ([B][N]).
+    Returns (dW [T][2][n][N] summed over frames in frame order, dllr [B][N])."""
+    fr = _u8(frozen)
+    N = len(fr)
+    n = N.bit_length() - 1
+    llr = _f32(llr).reshape(-1, N)
+    B = llr.shape[0]
+    W = _f64(W).reshape(T, 2, n, N)
+    dlam = _f64(dlam).reshape(B, N)
+    dW = np.zeros((T, 2, n, N), np.float64)
+    dl = np.zeros((B, N), np.float64)
+    _lib(prec).orc_wbp_backward_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), T, llr_max, _p(W, _f64p),
+                                      _p(dlam, _f64p), _p(dW, _f64p), _p(dl, _f64p))
+    return dW, dl
 
 
 def adam_step(w, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

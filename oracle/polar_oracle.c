@@ -688,9 +688,10 @@ static void g_partials(real a, real b, real* da, real* db) {
     else { *da = 0; *db = sgn(a); }
 }
 
-double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* u_true,
-                          int T, double llr_max, const double* W, double scale,
-                          double* dW /* [T][2][n][N], accumulated */, double* dllr /* N or NULL */) {
+/* Adjoint of the weighted BP given dlam = d loss / d lambda (N values; zero on
+ * frozen positions): accumulates dW (double) and writes dllr (optional). */
+void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int T, double llr_max,
+                            const double* W, const double* dlam, double* dW, double* dllr) {
     int n = ilog2(N);
     real lmax = (real)llr_max;
     size_t per = (size_t)2 * n * N;
@@ -698,8 +699,7 @@ double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const 
     double* save = (double*)malloc(sizeof(double) * per * T);
     uint8_t* uh = (uint8_t*)malloc(N);
     uint8_t ok;
-    double* lam = (double*)malloc(sizeof(double) * N);
-    orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, lam, NULL, &ok, save);
+    orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, NULL, NULL, &ok, save);
     /* the saved values are exact copies of `real` messages */
     real* Rch = (real*)malloc(sizeof(real) * N);  /* clipped channel */
     real* R0 = (real*)malloc(sizeof(real) * N);   /* frozen prior row */
@@ -707,19 +707,10 @@ double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const 
         Rch[i] = clip((real)llr[i], lmax);
         R0[i] = frozen[i] ? lmax : (real)0;
     }
-    double loss = 0.0;
     /* adjoints of the current message rows */
     real* aL = (real*)calloc((size_t)(n + 1) * N, sizeof(real));
     real* aR = (real*)calloc((size_t)(n + 1) * N, sizeof(real));
-    for (int i = 0; i < N; i++) {
-        if (frozen[i]) continue;
-        double sgn_u = u_true[i] ? 1.0 : -1.0;
-        double z = sgn_u * lam[i];
-        loss += softplus(z);
-        /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
-        double sig = 1.0 / (1.0 + exp(-z));
-        aL[0 * N + i] = (real)(scale * sgn_u * sig);
-    }
+    for (int i = 0; i < N; i++) aL[0 * N + i] = (real)dlam[i];
 #define SAVED_R(t, s, i) ((real)save[(size_t)(t) * per + ((size_t)0 * n + (s)) * N + (i)])
 #define SAVED_L(t, s, i) ((real)save[(size_t)(t) * per + ((size_t)1 * n + (s)) * N + (i)])
     /* value of row r of R during iteration t (0-based): row 0 constant, row r >= 1 saved */
@@ -809,12 +800,42 @@ double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const 
             dllr[i] = (fabs((real)llr[i]) <= lmax) ? (double)aL[n * N + i] : 0.0;
     free(save);
     free(uh);
-    free(lam);
     free(Rch);
     free(R0);
     free(aL);
     free(aR);
+}
+
+double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* u_true,
+                          int T, double llr_max, const double* W, double scale,
+                          double* dW /* [T][2][n][N], accumulated */, double* dllr /* N or NULL */) {
+    uint8_t* uh = (uint8_t*)malloc(N);
+    uint8_t ok;
+    double* lam = (double*)malloc(sizeof(double) * N);
+    double* dlam = (double*)calloc(N, sizeof(double));
+    orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, lam, NULL, &ok, NULL);
+    double loss = 0.0;
+    for (int i = 0; i < N; i++) {
+        if (frozen[i]) continue;
+        double sgn_u = u_true[i] ? 1.0 : -1.0;
+        double z = sgn_u * lam[i];
+        loss += softplus(z);
+        /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
+        double sig = 1.0 / (1.0 + exp(-z));
+        dlam[i] = (double)(real)(scale * sgn_u * sig);
+    }
+    orc_wbp_backward_frame(llr, N, frozen, T, llr_max, W, dlam, dW, dllr);
+    free(uh);
+    free(lam);
+    free(dlam);
     return loss * scale;
+}
+
+void orc_wbp_backward_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, int T, double llr_max,
+                            const double* W, const double* dlam, double* dW, double* dllr) {
+    for (int64_t f = 0; f < B; f++)
+        orc_wbp_backward_frame(llr + f * N, N, frozen, T, llr_max, W, dlam + f * N, dW,
+                               dllr ? dllr + f * N : NULL);
 }
 
 double orc_wbp_grad_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,

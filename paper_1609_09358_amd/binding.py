@@ -61,6 +61,10 @@ def lib():
             "scl_decode_batch": [vp, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
             "hybrid_decode_batch": [vp, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp],
             "polar_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
+            "wbp_forward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp],
+            "wbp_bce": [vp, vp, vp, i64, C.c_double, vp, vp, vp],
+            "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp, vp],
+            "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -262,6 +266,84 @@ def hybrid_decode_batch(code: PolarCode, llr: torch.Tensor, params: bp_params, L
     return out
 
 
+# --------------------------------------------------------------------------- weighted (learned) BP
+
+def wbp_forward(code: PolarCode, llr, W, llr_max=20.0, variant=0, save=False, out=None):
+    """T = W.shape[0] weighted iterations, no early stop.  Returns dict(llr_u, u_hat[, saved])."""
+    B = llr.shape[0]
+    T = W.shape[0]
+    _dev(llr, torch.float32, (B, code.N), "llr")
+    _dev(W, torch.float32, (T, 2, code.n, code.N), "W")
+    dev = llr.device
+    if out is None:
+        out = dict(llr_u=torch.empty((B, code.N), dtype=torch.float32, device=dev),
+                   u_hat=torch.empty((B, code.N), dtype=torch.uint8, device=dev))
+        if save:
+            out["saved"] = torch.empty((B, T, 2, code.n, code.N), dtype=torch.float32, device=dev)
+    _check(lib().wbp_forward(code.handle, _ptr(llr), B, _ptr(W), T, llr_max, variant, _ptr(out["llr_u"]),
+                             _ptr(out["u_hat"]), _ptr(out.get("saved")), _stream()))
+    return out
+
+
+def wbp_bce(code: PolarCode, llr_u, u_true, scale=None, want_loss=True):
+    """Per-frame BCE loss (times scale) and d loss / d llr_u; scale defaults to 1/(B k)."""
+    B = llr_u.shape[0]
+    _dev(llr_u, torch.float32, (B, code.N), "llr_u")
+    _dev(u_true, torch.uint8, (B, code.N), "u_true")
+    if scale is None:
+        scale = 1.0 / (B * code.k)
+    dlam = torch.empty_like(llr_u)
+    loss = torch.empty(B, dtype=torch.float32, device=llr_u.device) if want_loss else None
+    _check(lib().wbp_bce(code.handle, _ptr(llr_u), _ptr(u_true), B, float(scale), _ptr(loss), _ptr(dlam), _stream()))
+    return loss, dlam
+
+
+def wbp_backward(code: PolarCode, llr, W, saved, dlam, llr_max=20.0, variant=0, want_dllr=False):
+    """Weight gradient (summed over frames) and optionally d/d llr; `saved` is consumed."""
+    B = llr.shape[0]
+    T = W.shape[0]
+    _dev(llr, torch.float32, (B, code.N), "llr")
+    _dev(W, torch.float32, (T, 2, code.n, code.N), "W")
+    _dev(saved, torch.float32, (B, T, 2, code.n, code.N), "saved")
+    _dev(dlam, torch.float32, (B, code.N), "dlam")
+    dW = torch.empty_like(W)
+    dllr = torch.empty_like(llr) if want_dllr else None
+    _check(lib().wbp_backward(code.handle, _ptr(llr), B, _ptr(W), T, llr_max, variant, _ptr(saved), _ptr(dlam),
+                              _ptr(dW), _ptr(dllr), _stream()))
+    return dW, dllr
+
+
+def polar_adam_step(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    for name, t in (("w", w), ("g", g), ("m", m), ("v", v)):
+        _dev(t, torch.float32, tuple(w.shape), name)
+    _check(lib().polar_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), int(step), lr, beta1, beta2, eps,
+                                 _stream()))
+
+
+class WeightedBPLoss(torch.autograd.Function):
+    """loss = mean BCE of the weighted BP's soft outputs on the non-frozen bits.
+
+    forward(llr, W, u_true, code) runs wbp_forward (saving messages) and wbp_bce
+    in the library; backward runs wbp_backward.  Gradients flow to W (and to the
+    channel LLRs when they require grad)."""
+
+    @staticmethod
+    def forward(ctx, llr, W, u_true, code):
+        fw = wbp_forward(code, llr.detach().contiguous(), W.detach().contiguous(), save=True)
+        loss_f, dlam = wbp_bce(code, fw["llr_u"], u_true)
+        ctx.code = code
+        ctx.save_for_backward(llr.detach(), W.detach(), fw["saved"], dlam)
+        return loss_f.sum()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        llr, W, saved, dlam = ctx.saved_tensors
+        dlam = dlam * grad_out if grad_out.numel() == 1 and float(grad_out) != 1.0 else dlam
+        dW, dllr = wbp_backward(ctx.code, llr, W, saved, dlam.contiguous(), want_dllr=ctx.needs_input_grad[0])
+        return dllr, dW, None, None
+
+
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
-            "hybrid_decode_batch", "polar_workspace_size"]
+            "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
+            "wbp_backward", "polar_adam_step"]

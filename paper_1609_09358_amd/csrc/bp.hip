@@ -21,86 +21,10 @@
 // and LLR(x) are packed into bit words (N / 64 bits per lane), u_hat is
 // re-encoded with shifts inside words and lane exchanges across words, and
 // compared with x_hat; the CRC test uses per-nibble syndrome tables.
-#include <type_traits>
-
-#include "internal.hpp"
-#include "bp_geom.hpp"
+#include "bp_common.hpp"
 
 namespace polarhip {
 namespace bp {
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for_rev(F&& f) {  // E-1 down to B
-    if constexpr (B < E) {
-        f(std::integral_constant<int, E - 1>{});
-        static_for_rev<B, E - 1>(f);
-    }
-}
-
-__device__ __forceinline__ float g_ms(float a, float b) {
-    float m = fminf(fabsf(a), fabsf(b));
-    uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(m) | s);
-}
-
-__device__ __forceinline__ float clipf(float v, float m) { return fminf(fmaxf(v, -m), m); }
-
-// index bits of thread t in window k, register bits zero
-template <class G, int K>
-__device__ __forceinline__ int idx_base(int t) {
-    constexpr int b = G::wbase(K);
-    return (t & ((1 << b) - 1)) | ((t >> b) << (b + G::r));
-}
-
-// thread part of the LDS word address for boundary J in the layout of window K
-template <class G, int J, int K>
-__device__ __forceinline__ int lds_base(int t, int slot) {
-    int a = 0;
-#pragma unroll
-    for (int q = 0; q < G::P; ++q)
-        if ((t >> q) & 1) a += G::TAB.b[J].c[G::tpb(K, q)];
-#pragma unroll
-    for (int j = 0; j < G::SLOTB; ++j)
-        if ((slot >> j) & 1) a += G::TAB.b[J].c[G::n + j];
-    return a;
-}
-
-template <class G>
-__device__ __forceinline__ void frame_sync() {
-    if constexpr (G::NWAVES > 1) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-// re-layout one row from window KF to window KT across boundary J
-template <class G, int J, int KF, int KT, bool ISR>
-__device__ __forceinline__ void transpose_row(float (&row)[G::V], float* tb, int base_from, int base_to) {
-    constexpr int buf = ISR ? G::TAB.b[J].buf_r : G::TAB.b[J].buf_l;
-    float* p = tb + buf;
-#pragma unroll
-    for (int v = 0; v < G::V; ++v) p[base_from + G::reg_off(J, KF, v)] = row[v];
-    if constexpr (G::TAB.b[J].cross) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-#pragma unroll
-    for (int v = 0; v < G::V; ++v) row[v] = p[base_to + G::reg_off(J, KT, v)];
-}
 
 template <class G>
 __device__ __forceinline__ uint64_t load_bits(const uint8_t* src) {
@@ -169,11 +93,14 @@ __device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub
     return s == 0;
 }
 
-template <int NLOG, int RLOG, bool WEIGHTED>
+// SAVE (training): every message a column produces is also written to
+// saved[frame][iteration][direction][column][node], direction 0 = R (row s+1
+// of column s), 1 = L (row s), for the adjoint kernel.
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
     const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
-    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out) {
+    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, float* __restrict__ saved) {
     using G = Geom<NLOG, RLOG>;
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
     __shared__ float tb[G::TAB.words];
@@ -232,6 +159,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     float L0[V];
     while (true) {
         const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * N : nullptr;
+        float* Sit = SAVE ? saved + ((size_t)frame * max_iter + it) * 2 * n * N : nullptr;
         // ---------------- R sweep: columns 0..n-1
         static_for<0, G::NWIN>([&](auto KC) {
             constexpr int k = decltype(KC)::value;
@@ -253,6 +181,11 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
                         const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
                         Rm[s + 1][v] = clipf(wi * gi, lmax);
                         Rm[s + 1][v2] = clipf(__fmaf_rn(wj, gj, r2), lmax);
+                        if constexpr (SAVE) {
+                            float* sv = Sit + (size_t)(0 * n + s) * N + ib;
+                            sv[v << G::wbase(k)] = Rm[s + 1][v];
+                            sv[v2 << G::wbase(k)] = Rm[s + 1][v2];
+                        }
                     } else {
                         Rm[s + 1][v] = gi;  // |g| <= |r1| <= lmax: the clip is exact
                         Rm[s + 1][v2] = clipf(gj + r2, lmax);
@@ -289,6 +222,11 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
                         const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
                         Lm[s][v] = clipf(wi * gi, lmax);
                         Lm[s][v2] = clipf(__fmaf_rn(wj, gj, l2), lmax);
+                        if constexpr (SAVE) {
+                            float* sv = Sit + (size_t)(1 * n + s) * N + ib;
+                            sv[v << G::wbase(k)] = Lm[s][v];
+                            sv[v2 << G::wbase(k)] = Lm[s][v2];
+                        }
                     } else {
                         Lm[s][v] = gi;  // |g| <= |l1| <= lmax
                         Lm[s][v2] = clipf(gj + l2, lmax);
@@ -345,10 +283,12 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     // ---------------- outputs (window 0 layout: V consecutive nodes per thread)
     {
         const int ib = idx_base<G, 0>(t);
-        uint8_t* uo = u_hat + frame * N + ib;
-        const uint8_t* src = ub + ib;
+        if (u_hat) {
+            uint8_t* uo = u_hat + frame * N + ib;
+            const uint8_t* src = ub + ib;
 #pragma unroll
-        for (int v = 0; v < V; ++v) uo[v] = src[v];
+            for (int v = 0; v < V; ++v) uo[v] = src[v];
+        }
         if (llr_u) {
             float* lo = llr_u + frame * N + ib;
 #pragma unroll
@@ -356,7 +296,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
         }
         if (t == 0) {
             if (iters_out) iters_out[frame] = it;
-            ok_out[frame] = (uint8_t)(stop == 2 ? cok : (gok && cok));
+            if (ok_out) ok_out[frame] = (uint8_t)(stop == 2 ? cok : (gok && cok));
         }
     }
 }
@@ -364,16 +304,17 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
 // ------------------------------------------------------------------ dispatch
 
 using KernelFn = void (*)(CodeDev, const float*, int64_t, int, int, float, const float*, uint8_t*, float*,
-                          int32_t*, uint8_t*);
+                          int32_t*, uint8_t*, float*);
 
 struct Entry {
-    KernelFn plain, weighted;
+    KernelFn plain, weighted, weighted_save;
     int wg, fpw;
 };
 
 template <int NL, int RL>
 constexpr Entry make_entry() {
-    return Entry{&bp_kernel<NL, RL, false>, &bp_kernel<NL, RL, true>, Geom<NL, RL>::WG, Geom<NL, RL>::FPW};
+    return Entry{&bp_kernel<NL, RL, false, false>, &bp_kernel<NL, RL, true, false>, &bp_kernel<NL, RL, true, true>,
+                 Geom<NL, RL>::WG, Geom<NL, RL>::FPW};
 }
 
 // variants: register bits r = 2 or 3 (variant id = r)
@@ -425,7 +366,21 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
     if (blocks > (int64_t)INT32_MAX) return set_error(POLAR_ERR_INVALID_ARG, "bp: batch too large");
     bp::KernelFn fn = p->weights ? e->weighted : e->plain;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
-                       p->llr_max, p->weights, u_hat, llr_u, iters, ok);
+                       p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
+    return hip_check(hipGetLastError(), "bp_kernel launch");
+}
+
+polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,
+                            const float* W, int variant, uint8_t* u_hat, float* llr_u, uint8_t* ok, float* saved,
+                            hipStream_t stream) {
+    const int v = variant ? variant : bp_default_variant(code->n);
+    const bp::Entry* e = bp::lookup(code->n, v);
+    if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "wbp: no kernel variant for this block length");
+    if (B == 0) return POLAR_OK;
+    const int64_t blocks = (B + e->fpw - 1) / e->fpw;
+    bp::KernelFn fn = saved ? e->weighted_save : e->weighted;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, T, 0, llr_max, W,
+                       u_hat, llr_u, (int32_t*)nullptr, ok, saved);
     return hip_check(hipGetLastError(), "bp_kernel launch");
 }
 

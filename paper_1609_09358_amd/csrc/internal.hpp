@@ -63,6 +63,9 @@ polar_status hip_check(hipError_t e, const char* what);
 polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
                        uint8_t* u_hat, float* llr_u, int32_t* iters, uint8_t* ok,
                        hipStream_t stream);
+polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,
+                            const float* W, int variant, uint8_t* u_hat, float* llr_u, uint8_t* ok, float* saved,
+                            hipStream_t stream);
 bool bp_variant_supported(int n, int variant);
 int bp_default_variant(int n);
 int bp_list_variants(int n, int32_t* ids, int cap);

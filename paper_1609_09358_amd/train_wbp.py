@@ -1,0 +1,137 @@
+"""Training of the weighted (learned) min-sum BP on the GPU.
+
+Recipe (one step): draw a batch of random information bits and per-frame
+Eb/N0 uniform in [lo, hi] dB, encode (polar_encode), BPSK/AWGN LLRs
+(polar_channel_awgn), weighted BP forward with message saving (wbp_forward),
+binary cross-entropy on the non-frozen bits (wbp_bce), reverse-mode gradient
+(wbp_backward), Adam (polar_adam_step).  Every step of the decoder, its loss,
+gradient and update runs in the library's kernels; torch supplies device
+memory, the stream and the random draws of the workload.
+
+The weights start at 1 (plain min-sum BP) and are saved as float32 numpy
+arrays [T][2][n][N] together with the Adam moments and the step count, so a
+run can resume bit-exactly.
+"""
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import binding as PB
+
+
+def sigma2_of(ebn0_db: torch.Tensor, rate: float) -> torch.Tensor:
+    return 1.0 / (2.0 * rate * torch.pow(10.0, ebn0_db / 10.0))
+
+
+class Trainer:
+    def __init__(self, code: PB.PolarCode, T: int, batch: int, lr: float = 1e-3, ebn0=(1.0, 4.0), seed: int = 1,
+                 llr_max: float = 20.0):
+        self.code, self.T, self.B, self.lr, self.ebn0, self.llr_max = code, T, batch, lr, ebn0, llr_max
+        dev = torch.device("cuda")
+        shape = (T, 2, code.n, code.N)
+        self.W = torch.ones(shape, dtype=torch.float32, device=dev)
+        self.m = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.step = 0
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        self.out = dict(llr_u=torch.empty((batch, code.N), dtype=torch.float32, device=dev),
+                        u_hat=torch.empty((batch, code.N), dtype=torch.uint8, device=dev),
+                        saved=torch.empty((batch,) + shape, dtype=torch.float32, device=dev))
+
+    def frames(self, B=None, ebn0=None):
+        """A fresh batch: (u [B][N], llr [B][N])."""
+        B = B or self.B
+        code = self.code
+        info = torch.randint(0, 2, (B, code.K), generator=self.gen, device="cuda", dtype=torch.uint8)
+        u, x = PB.polar_encode(code, info, want_u=True)
+        lo, hi = self.ebn0 if ebn0 is None else (ebn0, ebn0)
+        e = lo + (hi - lo) * torch.rand(B, generator=self.gen, device="cuda")
+        z = torch.randn((B, code.N), generator=self.gen, device="cuda")
+        llr = PB.polar_channel_awgn(x, z, sigma2_of(e, code.K / code.N).float().contiguous())
+        return info, u, llr
+
+    def train_step(self):
+        _, u, llr = self.frames()
+        fw = PB.wbp_forward(self.code, llr, self.W, llr_max=self.llr_max, save=True, out=self.out)
+        loss, dlam = PB.wbp_bce(self.code, fw["llr_u"], u)
+        dW, _ = PB.wbp_backward(self.code, llr, self.W, fw["saved"], dlam, llr_max=self.llr_max)
+        self.step += 1
+        PB.polar_adam_step(self.W, dW, self.m, self.v, self.step, lr=self.lr)
+        return loss
+
+    def save(self, path):
+        np.savez(path, W=self.W.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 step=np.array(self.step), rng=self.gen.get_state().cpu().numpy())
+
+    def load(self, path):
+        z = np.load(path)
+        self.W.copy_(torch.from_numpy(z["W"]))
+        self.m.copy_(torch.from_numpy(z["m"]))
+        self.v.copy_(torch.from_numpy(z["v"]))
+        self.step = int(z["step"])
+        self.gen.set_state(torch.from_numpy(z["rng"]))
+
+
+def train(N=256, K=128, crc_bits=8, T=10, frames=1_000_000, batch=4096, lr=1e-3, ebn0=(1.0, 4.0), design=2.5,
+          seed=1, log_every=20, verbose=True):
+    """Train and return (trainer, history); `frames` / `batch` steps."""
+    code = PB.PolarCode(N, K, crc_bits, 0, design)
+    tr = Trainer(code, T, batch, lr, ebn0, seed)
+    steps = math.ceil(frames / batch)
+    hist = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        loss = tr.train_step()
+        if (s + 1) % log_every == 0 or s == 0 or s + 1 == steps:
+            lv = float(loss.sum())
+            hist.append((s + 1, lv))
+            if verbose:
+                print(json.dumps({"step": s + 1, "loss": lv, "s": round(time.perf_counter() - t0, 2)}), flush=True)
+    torch.cuda.synchronize()
+    return tr, hist
+
+
+def info_of(code: PB.PolarCode, u_hat: torch.Tensor) -> torch.Tensor:
+    """Information bits of decoded u vectors: the first K non-frozen positions
+    (the CRC occupies the last c)."""
+    idx = torch.as_tensor(code.info_pos[: code.K], dtype=torch.long, device=u_hat.device)
+    return u_hat.index_select(1, idx)
+
+
+def fer(decode, tr: Trainer, ebn0: float, frames: int, batch: int = 65536):
+    """Frame error rate of `decode(llr) -> info_hat [B][K]` at one Eb/N0 on
+    fresh frames from the trainer's generator."""
+    err = 0
+    done = 0
+    while done < frames:
+        b = min(batch, frames - done)
+        info, _, llr = tr.frames(b, ebn0=ebn0)
+        err += int((decode(llr) != info).any(dim=1).sum())
+        done += b
+    return err / frames
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--K", type=int, default=128)
+    ap.add_argument("--crc", type=int, default=8)
+    ap.add_argument("--T", type=int, default=10)
+    ap.add_argument("--frames", type=int, default=1_000_000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    tr, _ = train(a.N, a.K, a.crc, a.T, a.frames, a.batch, a.lr)
+    if a.out:
+        tr.save(a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,142 @@
+"""GPU parity of the weighted (learned) BP: forward, loss, adjoint, Adam.
+
+Forward messages and the per-frame adjoint follow the oracle's operation order,
+so they are compared bit for bit with the oracle's float build (given the same
+d loss / d lambda); the frame sum of the weight gradient is accumulated in
+double in frame order on both sides, so it matches too.  The loss gradient
+itself (computed in double on the GPU) and the end-to-end gradient are
+compared with the double build within tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1609_09358_amd import binding as PB
+from paper_1609_09358_amd import inputs
+
+pytestmark = pytest.mark.gpu
+POLY = {0: 0, 8: 0x07, 16: 0x1021, 24: 0x864CFB}
+
+
+def frames(N, K, c, ebn0, B, seed):
+    code = PB.PolarCode(N, K, c, 0, 2.5)
+    info = inputs.info_bits(B, K, seed)
+    u, x = O.encode_batch(info, K, c, POLY[c], code.frozen)
+    llr = O.channel_llr(x, inputs.noise(B, N, seed), O.sigma2(ebn0, K / N))
+    return code, u, llr
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_w(T, n, N, seed, lo=0.5, hi=1.5):
+    return np.random.default_rng(seed).uniform(lo, hi, (T, 2, n, N)).astype(np.float32)
+
+
+@pytest.mark.parametrize("N,K,c,T", [(16, 8, 0, 3), (128, 64, 0, 5), (256, 128, 8, 10), (1024, 512, 24, 4)])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_forward_bit_exact(N, K, c, T, variant):
+    n = N.bit_length() - 1
+    B = 21
+    code, u, llr = frames(N, K, c, 1.5, B, seed=N + T)
+    W = rand_w(T, n, N, seed=T)
+    out = PB.wbp_forward(code, dev(llr), dev(W), variant=variant, save=True)
+    lam = host(out["llr_u"])
+    saved = host(out["saved"])
+    for f in range(B):
+        ref = O.bp_frame(llr[f], code.frozen, max_iter=T, stop=0, W=W.astype(np.float64), save=True, prec="f32")
+        assert np.array_equal(lam[f], ref["llr_u"].astype(np.float32))
+        assert np.array_equal(saved[f], ref["save"].astype(np.float32))
+
+
+def test_unit_weights_equal_plain_bp():
+    N, K, c, T = 1024, 512, 16, 7
+    code, u, llr = frames(N, K, c, 2.0, 32, seed=4)
+    W = np.ones((T, 2, 10, N), np.float32)
+    a = PB.wbp_forward(code, dev(llr), dev(W))
+    b = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=0, soft=True)
+    assert np.array_equal(host(a["llr_u"]), host(b["llr_u"]))
+    assert np.array_equal(host(a["u_hat"]), host(b["u_hat"]))
+
+
+@pytest.mark.parametrize("N,K,c,T", [(16, 8, 0, 3), (128, 64, 0, 4), (256, 128, 8, 10), (1024, 512, 24, 3)])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_backward_bit_exact_given_dlam(N, K, c, T, variant):
+    n = N.bit_length() - 1
+    B = 19
+    code, u, llr = frames(N, K, c, 1.0, B, seed=7 * N + T)
+    W = rand_w(T, n, N, seed=N)
+    llr_d, W_d = dev(llr), dev(W)
+    fw = PB.wbp_forward(code, llr_d, W_d, variant=variant, save=True)
+    _, dlam = PB.wbp_bce(code, fw["llr_u"], dev(u))
+    dW, dllr = PB.wbp_backward(code, llr_d, W_d, fw["saved"], dlam, variant=variant, want_dllr=True)
+    dlam_h = host(dlam).astype(np.float64)
+    ref_dW, ref_dllr = O.wbp_backward(llr, code.frozen, T, W.astype(np.float64), dlam_h, prec="f32")
+    assert np.array_equal(host(dW), ref_dW.astype(np.float32))
+    assert np.array_equal(host(dllr), ref_dllr.astype(np.float32))
+    assert np.abs(ref_dW).sum() > 0
+
+
+@pytest.mark.parametrize("T", [3, 10])
+def test_end_to_end_gradient(T):
+    """Loss and weight gradient at N = 256 (the training workload's code).
+
+    Against the float oracle the forward decisions are identical, the adjoint
+    is linear in d loss / d lambda, and that vector differs only through the
+    device's and the host's double exp (at most an ulp after rounding to
+    float), so the gradients agree to float rounding at any T.  Against the
+    double oracle, fp32 rounding of the messages grows with every iteration
+    (min/clip decisions flip on near-ties), so that comparison is made at
+    T = 3 only, as for plain BP."""
+    N, K, c, B = 256, 128, 8, 64
+    n = 8
+    code, u, llr = frames(N, K, c, 2.0, B, seed=99)
+    W = rand_w(T, n, N, seed=5, lo=0.8, hi=1.2)
+    llr_d, W_d = dev(llr), dev(W)
+    fw = PB.wbp_forward(code, llr_d, W_d, save=True)
+    loss, dlam = PB.wbp_bce(code, fw["llr_u"], dev(u))
+    dW, _ = PB.wbp_backward(code, llr_d, W_d, fw["saved"], dlam)
+    g = host(dW).astype(np.float64)
+    tot = float(host(loss).astype(np.float64).sum())
+    l32, g32 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), prec="f32")
+    assert abs(tot - l32) <= 1e-5 * max(1.0, abs(l32))
+    assert np.max(np.abs(g - g32)) <= 1e-5 * np.abs(g32).max()
+    if T <= 3:
+        l64, g64 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64))
+        assert abs(tot - l64) <= 1e-5 * max(1.0, abs(l64))
+        assert np.max(np.abs(g - g64)) <= 1e-4 * np.abs(g64).max()
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=5000).astype(np.float32)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    wd, md, vd = dev(w), dev(m), dev(v)
+    w64, m64, v64 = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 6):
+        g = rng.normal(size=5000).astype(np.float32)
+        PB.polar_adam_step(wd, dev(g), md, vd, step)
+        O.adam_step(w64, g.astype(np.float64), m64, v64, step)
+    np.testing.assert_allclose(host(wd), w64, rtol=1e-5, atol=1e-6)
+
+
+def test_autograd_function():
+    N, K, c, T, B = 256, 128, 8, 4, 16
+    code, u, llr = frames(N, K, c, 2.0, B, seed=12)
+    W = torch.ones((T, 2, 8, N), device="cuda", requires_grad=True)
+    llr_d = dev(llr)
+    loss = PB.WeightedBPLoss.apply(llr_d, W, dev(u), code)
+    loss.backward()
+    fw = PB.wbp_forward(code, llr_d, W.detach(), save=True)
+    _, dlam = PB.wbp_bce(code, fw["llr_u"], dev(u))
+    dW, _ = PB.wbp_backward(code, llr_d, W.detach(), fw["saved"], dlam)
+    assert torch.equal(W.grad, dW)
+    assert float(loss) > 0
