@@ -1,12 +1,23 @@
-"""Benchmark: decoded information throughput of the hybrid BP -> CA-SCL decoder.
+"""Benchmark: decoded information throughput of the learned hybrid decoder.
 
 Workload (synthetic, seeded): polar code N = 1024, K = 512 information bits
-plus CRC-16, frozen set by Gaussian approximation at 2.5 dB; uniform random
-information bits, BPSK over AWGN at Eb/N0 = 2.5 dB (rate K/N).  One step is
-one hybrid decode of a resident batch of frames: min-sum BP (at most 200
-iterations, re-encoding stop, CRC verdict), device-side compaction of the
-failed frames, CA-SCL with list size 8 on them, merge.  The LLRs are in HBM
-before the timed region starts; host transfers are excluded.
+plus CRC-24, frozen set by Gaussian approximation at 2.5 dB; uniform random
+information bits, BPSK over AWGN at Eb/N0 = 2.5 dB (rate K/N).
+
+One step is one hybrid decode of a resident batch of frames: weighted
+(learned) min-sum BP with at most T = 20 iterations (re-encoding stop, CRC
+verdict), device-side compaction of the frames whose verdict is not ok,
+CA-SCL with list size 32 on them, merge.  The LLRs are in HBM before the
+timed region starts; host transfers are excluded.
+
+The learned weights are fitted before timing (untimed, seeded): the
+normalized min-sum scale with the fewest BP failures on validation frames,
+then Adam on the binary cross-entropy of the soft outputs, then a coordinate
+search over per-iteration weight blocks on the failure rate.  The plain hybrid
+(unweighted BP, at most 200 iterations, then the same CA-SCL) decodes the same
+frames for comparison; the throughput counts only if the learned decoder's
+frame error rate does not exceed the upper 95% Clopper-Pearson bound of the
+plain decoder's on a common set of frames.
 
 Printed: one JSON line with the throughput, a roofline entry for the kernel
 that takes most of the step's time (measured with HIP events on the stream
@@ -25,10 +36,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+# MI355X published figures
 HBM_PEAK_GBS = 8000.0
 CU, LANES, CLOCK_GHZ = 256, 64, 2.4
 VALU_PEAK_GOPS = CU * LANES * CLOCK_GHZ  # one 32-bit VALU operation per lane per clock
+
+POLY24 = 0x864CFB
 
 
 def parse():
@@ -38,11 +51,21 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=65536, help="frames per step")
     ap.add_argument("--ebn0", type=float, default=2.5)
+    ap.add_argument("--T", type=int, default=20, help="learned BP iterations")
+    ap.add_argument("--L", type=int, default=32, help="list size")
+    ap.add_argument("--train-frames", type=int, default=1_000_000)
+    ap.add_argument("--fer-frames", type=int, default=1 << 20, help="frames per decoder for the FER comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
+
+
+def cp_upper(k, n, conf=0.95):
+    """Upper end of the two-sided Clopper-Pearson interval of k errors in n."""
+    from scipy.stats import beta
+    return 1.0 if k >= n else float(beta.ppf(1 - (1 - conf) / 2, k + 1, n - k))
 
 
 def main():
@@ -56,13 +79,33 @@ def main():
 
     from paper_1609_09358_amd import binding as PB
     from paper_1609_09358_amd import inputs
+    from paper_1609_09358_amd import train_wbp as TW
 
     torch.cuda.set_device(0)
-    N, K, C, L, IMAX, DESIGN = 1024, 512, 16, 8, 200, 2.5
+    N, K, C, DESIGN, T, L, IMAX = 1024, 512, 24, 2.5, args.T, args.L, 200
+    n = N.bit_length() - 1
     B = args.frames
     R = K / N
     sigma2 = 1.0 / (2.0 * R * 10.0 ** (args.ebn0 / 10.0))
-    code = PB.PolarCode(N, K, C, 0, DESIGN)
+    code = PB.PolarCode(N, K, C, POLY24, DESIGN)
+    log = lambda **kw: print(json.dumps(kw), file=sys.stderr, flush=True)
+
+    # ---- learned weights (untimed): scale fit, Adam on BCE, block search
+    t_fit = time.perf_counter()
+    tr = TW.Trainer(code, T, 4096, lr=1e-4, ebn0=(2.0, 3.0), seed=1609)
+    val_gen = TW.Trainer(code, 1, 16, seed=9358)
+    _, _, val_llr = val_gen.frames(1 << 17, ebn0=args.ebn0)
+    W0, alpha, rate0 = TW.fit_scale(code, val_llr, T)
+    tr.W.copy_(W0)
+    for _ in range(max(1, args.train_frames // tr.B)):
+        tr.train_step()
+    rate_adam = TW.bp_fail_rate(code, val_llr, tr.W, T)
+    W, rate_ref = TW.refine_blocks(code, val_llr, tr.W.clone())
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t_fit
+    log(stage="weights", alpha=alpha, val_fail_scale=rate0, val_fail_adam=rate_adam, val_fail_refined=rate_ref,
+        seconds=round(fit_s, 1))
+    del val_llr, tr
 
     # ---- synthetic frames, resident in HBM (untimed)
     seed = 20161
@@ -75,32 +118,56 @@ def main():
     del x_d
     torch.cuda.synchronize()
 
-    dec = PB.HybridDecoder(code, max_iter=IMAX, L=L, stop=1)
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
-    out = dec(llr, stats=stats)
+    learned = PB.HybridDecoder(code, max_iter=T, L=L, stop=1, weights=W)
+    plain = PB.HybridDecoder(code, max_iter=IMAX, L=L, stop=1)
+    out = learned(llr)
+    out_p = plain(llr)
     torch.cuda.synchronize()
 
-    # ---- timed region: K hybrid steps
-    for _ in range(args.warmup):
-        dec(llr, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dec(llr, out=out)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def run_steps(dec, o, steps, warmup):
+        for _ in range(warmup):
+            dec(llr, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dec(llr, out=o)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # ---- timed region: K learned-hybrid steps
+    elapsed = run_steps(learned, out, args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
     gbps = B * K * args.steps / elapsed / 1e9
+    # the plain hybrid on the same resident frames, for comparison
+    elapsed_p = run_steps(plain, out_p, args.steps, args.warmup)
+    gbps_plain = B * K * args.steps / elapsed_p / 1e9
 
-    # ---- decoding statistics of one step
-    stats.zero_()
-    dec(llr, out=out, stats=stats)
-    torch.cuda.synchronize()
-    st = stats.cpu().numpy()
-    info_hat = out["info"].cpu().numpy()
-    fer = float(np.mean(np.any(info_hat != info, axis=1)))
-    gamma = float(st[2]) / B
-    mean_iters = float(st[3]) / B
+    # ---- statistics of one step of each
+    def one(dec, o):
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        dec(llr, out=o, stats=st)
+        torch.cuda.synchronize()
+        return st.cpu().numpy()
+
+    st = one(learned, out)
+    st_p = one(plain, out_p)
+    fer_batch = float(np.mean(np.any(out["info"].cpu().numpy() != info, axis=1)))
+
+    # ---- FER of both on common frames (fresh, seeded, generated on the device)
+    fer_gen = TW.Trainer(code, 1, 16, seed=4242)
+    nf, err_l, err_p, only_l, only_p = 0, 0, 0, 0, 0
+    while nf < args.fer_frames:
+        b = min(B, args.fer_frames - nf)
+        inf_f, _, llr_f = fer_gen.frames(b, ebn0=args.ebn0)
+        el = (learned(llr_f)["info"] != inf_f).any(dim=1)
+        ep = (plain(llr_f)["info"] != inf_f).any(dim=1)
+        err_l += int(el.sum())
+        err_p += int(ep.sum())
+        only_l += int((el & ~ep).sum())
+        only_p += int((ep & ~el).sum())
+        nf += b
+    fer_l, fer_p = err_l / nf, err_p / nf
+    valid = fer_l <= cp_upper(err_p, nf)
 
     # ---- per-kernel durations with events on the launch stream
     stream = torch.cuda.current_stream()
@@ -121,7 +188,7 @@ def main():
                   iters=torch.empty(B, dtype=torch.int32, device="cuda"),
                   ok=torch.empty(B, dtype=torch.uint8, device="cuda"))
     reps = max(3, args.steps // 2)
-    bp_ms = timed(lambda: PB.bp_decode_batch(code, llr, max_iter=IMAX, stop=1, out=bp_out), reps)
+    bp_ms = timed(lambda: PB.bp_decode_batch(code, llr, max_iter=T, stop=1, weights=W, out=bp_out), reps)
     fail_ids = torch.nonzero(bp_out["ok"] == 0).flatten().to(torch.int32).contiguous()
     nfail = int(fail_ids.numel())
     scl_out = dict(u_hat=torch.empty((B, N), dtype=torch.uint8, device="cuda"),
@@ -133,40 +200,50 @@ def main():
                    reps) if nfail else 0.0
     iter_sum = int(bp_out["iters"].sum().item())
 
-    # algorithmic work of the BP kernel: per PE and sweep 2 additions, 2
-    # evaluations of g (magnitude minimum and sign product: 2 operations each)
-    # and 2 clips = 8 operations; n*N/2 PEs and 2 sweeps per iteration
-    n = N.bit_length() - 1
-    bp_ops = 8.0 * n * N * iter_sum
-    bp_gops = bp_ops / (bp_ms * 1e-3) / 1e9
+    # algorithmic work of the weighted BP kernel: per PE and sweep 2 additions,
+    # 2 evaluations of g (magnitude minimum and sign product: 2 operations
+    # each), 2 weight multiplications and 2 clips = 10 operations; n*N/2 PEs
+    # and 2 sweeps per iteration
+    bp_ops = 10.0 * n * N * iter_sum
     # algorithmic work of the SCL kernel: L * n * N / 2 f/g evaluations per frame
     scl_ops = float(L * n * N // 2) * nfail
     dominant = "bp_kernel" if bp_ms >= scl_ms else "scl_kernel"
+    ach = bp_ops / (bp_ms * 1e-3) / 1e12 if dominant == "bp_kernel" else scl_ops / (scl_ms * 1e-3) / 1e12
     roofline = {
         "kernel": dominant,
         "bound": "alu",
-        "achieved": round(bp_gops / 1e3, 3) if dominant == "bp_kernel" else round(scl_ops / (scl_ms * 1e-3) / 1e12, 4),
+        "achieved": round(ach, 4),
         "peak": round(VALU_PEAK_GOPS / 1e3, 2),
         "unit": "Tops/s",
-        "frac": None,
+        "frac": round(ach / (VALU_PEAK_GOPS / 1e3), 4),
         "traffic": None,
     }
-    roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
-    hbm_bytes_bp = B * (4 * N + N + 5)
+    gamma = float(st[2]) / B
     extra = {
-        "fer": fer,
+        "valid_fer_le_plain": bool(valid),
+        "fer_learned": fer_l,
+        "fer_plain": fer_p,
+        "fer_frames": nf,
+        "fer_plain_cp95_upper": cp_upper(err_p, nf),
+        "mcnemar_only_learned_wrong": only_l,
+        "mcnemar_only_plain_wrong": only_p,
+        "fer_timed_batch": fer_batch,
+        "plain_hybrid_Gbps": round(gbps_plain, 4),
+        "speedup_vs_plain": round(gbps / gbps_plain, 3),
         "bp_fail_rate": gamma,
-        "mean_bp_iterations": mean_iters,
+        "bp_fail_rate_plain": float(st_p[2]) / B,
+        "mean_bp_iterations": float(st[3]) / B,
+        "mean_bp_iterations_plain": float(st_p[3]) / B,
         "kernel_ms": {"bp_kernel": round(bp_ms, 4), "scl_kernel": round(scl_ms, 4)},
         "scl_frames": nfail,
-        "bp_hbm_GBps": round(hbm_bytes_bp / (bp_ms * 1e-3) / 1e9, 1),
-        "hbm_peak_GBps": HBM_PEAK_GBS,
+        "weights": {"alpha": alpha, "val_fail_scale": rate0, "val_fail_adam": rate_adam,
+                    "val_fail_refined": rate_ref, "fit_seconds": round(fit_s, 1)},
         "eq1_theory_Gbps": None,
     }
     # eq. (1) of the paper with the measured parts
-    t_bp = B * K / (bp_ms * 1e-3) / 1e9
-    t_scl = (nfail * K / (scl_ms * 1e-3) / 1e9) if nfail else float("inf")
     if nfail:
+        t_bp = B * K / (bp_ms * 1e-3) / 1e9
+        t_scl = nfail * K / (scl_ms * 1e-3) / 1e9
         extra["eq1_theory_Gbps"] = round(t_bp * t_scl / (t_scl + gamma * t_bp), 3)
 
     if args.copy_calibration:
@@ -179,7 +256,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(info, z, sigma2, N, K, C, L, IMAX, DESIGN, args.cpu_seconds)
+        cpu = cpu_baseline(info, z, sigma2, code.frozen, N, K, C, L, T, W.cpu().numpy().astype(np.float64),
+                           args.cpu_seconds)
 
     line = {
         "metric": "decoded info Gbit/s, N=1024 R=1/2 hybrid at FER≤plain, Eb/N0 2.5 dB",
@@ -195,8 +273,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "plain hybrid: min-sum BP i_max=200 (re-encoding stop, CRC-16 verdict) -> CA-SCL L=8; "
-                        "N=1024 K=512 CRC-16, GA design 2.5 dB, BPSK/AWGN Eb/N0 2.5 dB",
+            "workload": f"learned hybrid: weighted min-sum BP T={T} (re-encoding stop, CRC-24 verdict) -> CA-SCL "
+                        f"L={L}; N=1024 K=512 CRC-24, GA design 2.5 dB, BPSK/AWGN Eb/N0 {args.ebn0} dB; compared "
+                        f"with plain hybrid BP i_max={IMAX} -> CA-SCL L={L} on the same frames",
             "frames_per_step": B,
             "ebn0_db": args.ebn0,
         },
@@ -207,28 +286,37 @@ def main():
     print(json.dumps(line))
 
 
-def cpu_baseline(info, z, sigma2, N, K, C, L, IMAX, DESIGN, target_s):
-    """The oracle (double precision, as written) decoding the first frames of
-    the same workload on the host cores, one thread per slice."""
+def cpu_baseline(info, z, sigma2, frozen, N, K, C, L, T, W64, target_s):
+    """The oracle (double precision, as written) running the same learned
+    hybrid on the first frames of the same workload on the host cores, one
+    thread per slice."""
     import oracle as O
 
     threads = min(16, os.cpu_count() or 1)
-    fr = O.ga_frozen(N, K + C, DESIGN, K / N)
+    fr = np.asarray(frozen, np.uint8)
+
+    def llr_of(M):
+        u, x = O.encode_batch(info[:M], K, C, POLY24, fr)
+        return O.channel_llr(x, z[:M].astype(np.float64), sigma2)
+
+    def dec(llr_part):
+        return O.hybrid_batch(llr_part, fr, K, C, POLY24, T, L, W=W64)
+
     # calibrate on a few frames, then size the sample for ~target_s seconds
-    M0 = threads
-    u, x = O.encode_batch(info[:M0], K, C, 0x1021, fr)
-    llr0 = O.channel_llr(x, z[:M0].astype(np.float64), sigma2)
+    M0 = 4 * threads
+    llr0 = llr_of(M0)
+    chunks0 = np.array_split(np.arange(M0), threads)
     t0 = time.perf_counter()
-    O.hybrid_batch(llr0, fr, K, C, 0x1021, IMAX, L)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda idx: dec(llr0[idx]), chunks0))
     per_frame = (time.perf_counter() - t0) / M0
-    M = int(max(threads, min(len(info), target_s * threads / max(per_frame, 1e-6))))
-    M = (M // threads) * threads
-    u, x = O.encode_batch(info[:M], K, C, 0x1021, fr)
-    llr = O.channel_llr(x, z[:M].astype(np.float64), sigma2)
+    M = int(max(threads, min(len(info), target_s / max(per_frame, 1e-6))))
+    M = max(threads, (M // threads) * threads)
+    llr = llr_of(M)
     chunks = np.array_split(np.arange(M), threads)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        outs = list(ex.map(lambda idx: O.hybrid_batch(llr[idx], fr, K, C, 0x1021, IMAX, L), chunks))
+        outs = list(ex.map(lambda idx: dec(llr[idx]), chunks))
     dt = time.perf_counter() - t0
     info_hat = np.concatenate([o["info"] for o in outs])
     return {
@@ -237,7 +325,7 @@ def cpu_baseline(info, z, sigma2, N, K, C, L, IMAX, DESIGN, target_s):
         "cores": threads,
         "kind": "oracle",
         "sample": f"first {M} frames of the same workload (same info bits and noise), double-precision oracle "
-                  f"hybrid, {dt:.1f} s",
+                  f"learned hybrid T={T} L={L} with the same weights, {dt:.1f} s",
         "fer": float(np.mean(np.any(info_hat != info[:M], axis=1))),
     }
 

@@ -196,6 +196,18 @@ polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64
 polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,
                                   const bp_params* params, size_t* bytes);
 
+/* Per-workgroup LDS budget of the list decoder in bytes, 4096..163840, or 0
+ * (the default: a CU's 160 KB divided by the number of the kernel's one-wave
+ * workgroups its registers let share a CU).  A list decode keeps as much of
+ * its state in LDS as the budget allows: when it does not all fit, the per-bit
+ * trace moves to the workspace's global slice first, then the largest LLR
+ * tree levels do.  A smaller budget lets more workgroups share a CU.
+ * Process-wide; it applies to plans made afterwards, so query workspace sizes
+ * again after a change.  POLAR_ERR_INVALID_ARG outside the range.  Host only;
+ * polar_get_scl_lds_budget returns the setting (0 = automatic). */
+polar_status polar_set_scl_lds_budget(int64_t bytes);
+int64_t polar_get_scl_lds_budget(void);
+
 /* ---------------------------------------------------------------------------
  * Weighted (learned) min-sum BP -- not in the paper; trains the weights of the
  * weighted form of bp_decode_batch.  W: dev float [T][2][n][N] as in bp_params.

@@ -65,11 +65,14 @@ def lib():
             "wbp_bce": [vp, vp, vp, i64, C.c_double, vp, vp, vp],
             "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp, vp],
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+            "polar_set_scl_lds_budget": [i64],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.polar_get_scl_lds_budget.argtypes = []
+        L.polar_get_scl_lds_budget.restype = i64
         L.polar_free_code.argtypes = [vp]
         L.polar_free_code.restype = None
         _lib = L
@@ -210,6 +213,15 @@ def polar_workspace_size(code: PolarCode, B, L, hybrid_params=None):
     return s.value
 
 
+def polar_set_scl_lds_budget(nbytes: int):
+    """Per-workgroup LDS budget of the list decoder (0 = default); process-wide."""
+    _check(lib().polar_set_scl_lds_budget(int(nbytes)))
+
+
+def polar_get_scl_lds_budget() -> int:
+    return int(lib().polar_get_scl_lds_budget())
+
+
 def scl_decode_batch(code: PolarCode, llr: torch.Tensor, L, frame_ids=None, out=None, workspace=None):
     rows = llr.shape[0]
     _dev(llr, torch.float32, (rows, code.N), "llr")
@@ -346,4 +358,4 @@ class WeightedBPLoss(torch.autograd.Function):
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
-            "wbp_backward", "polar_adam_step"]
+            "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget"]

@@ -71,10 +71,14 @@ int bp_default_variant(int n);
 int bp_list_variants(int n, int32_t* ids, int cap);
 
 struct SclPlan {
-    int gl;            // levels >= gl live in global memory
-    size_t lds_bytes;  // dynamic LDS per workgroup
-    size_t glob_per_wg;  // global bytes per workgroup (levels >= gl, LLRs and partial sums)
-    int grid;          // workgroups launched
+    int gl;              // LLR levels >= gl live in the global slice
+    size_t lds_bytes;    // dynamic LDS per workgroup
+    int trace_glob;      // 1: the per-bit trace lives in the global slice
+    int trace_chunk;     // information bits per read-back chunk when trace_glob
+    int tb_off;          // LDS byte offset of the trace when !trace_glob
+    size_t trace_off;    // byte offset of the trace inside the global slice
+    size_t glob_per_wg;  // global slice bytes per workgroup (levels >= gl, trace)
+    int grid;            // workgroups launched
 };
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan);
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,

@@ -27,6 +27,14 @@
 // running syndrome (linear in the decided bits); the decoded bits of the
 // chosen path are recovered from a per-information-bit trace of
 // (parent, bit).
+//
+// A frame's decode is a long chain of dependent steps, so throughput comes
+// from many frames in flight: the kernel is held to 128 VGPRs (four waves per
+// SIMD) and the LDS state is sized to let sixteen one-wave workgroups share a
+// CU.  What does not fit moves to the workgroup's global slice: first the
+// trace (written once per information bit, read back in chunks for the
+// traceback), then the largest tree levels.
+#include <atomic>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -122,17 +130,22 @@ __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float m
 }
 
 struct Layout {
-    int gl;   // LLR levels < gl in LDS, the others in the workgroup's global slice
-    int sl;   // LDS floats per slot (LLR heap, padded)
-    int pw;   // partial-sum words per slot (levels >= 5)
+    int gl;      // LLR levels < gl in LDS, the others in the workgroup's global slice
+    int sl;      // LDS floats per slot: levels BL..gl-1, level d at offset 2^d - 2^BL, padded
+    int pw;      // partial-sum words per slot (levels >= 5)
+    int tg;      // 1: the trace lives in the global slice and is read back in chunks
+    int tchunk;  // information bits per chunk of the read-back trace
+    int64_t gbytes;  // bytes of the global slice per workgroup
+    int64_t toff;    // byte offset of the trace inside the slice
+    int tboff;       // byte offset of the LDS trace (at least N: dec[] sits below it)
 };
 
 template <int L, int BL>
-__global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __restrict__ llr,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
                                                  uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
-                                                 float* __restrict__ pm_out, float* __restrict__ glam_all,
+                                                 float* __restrict__ pm_out, unsigned char* __restrict__ glob_all,
                                                  Layout lay) {
     constexpr int BS = 1 << BL;  // bits per block
     extern __shared__ __attribute__((aligned(16))) unsigned char sm[];
@@ -144,10 +157,12 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
     uint32_t* psw = reinterpret_cast<uint32_t*>(slam + L * SL);   // [L][PW]
     uint32_t* mets = psw + L * PW;                                // [64]
     int32_t* inv = reinterpret_cast<int32_t*>(mets + 64);         // [L]
-    uint8_t* tbk = reinterpret_cast<uint8_t*>(inv + L);           // [k][L]
+    uint8_t* tbk = sm + lay.tboff;                                // [k][L] unless tg
     uint8_t* dec = reinterpret_cast<uint8_t*>(slam);              // [N], reuses the LLR area at the end
 
-    float* glam = glam_all ? glam_all + (size_t)blockIdx.x * L * N : nullptr;
+    unsigned char* gbase = glob_all ? glob_all + (size_t)blockIdx.x * (size_t)lay.gbytes : nullptr;
+    float* glam = reinterpret_cast<float*>(gbase);            // [L][N], levels >= gl
+    uint8_t* tbg = lay.tg ? gbase + lay.toff : nullptr;       // [k][L] when tg
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
     for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
@@ -178,35 +193,57 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
                     const int items = act << d;
                     const int myp = get_byte(ptrL, d + 1);
                     const int mypp = get_byte(ptrP, d);
-                    for (int it = lane; it < items; it += 64) {
-                        const int slot = it >> d;
-                        const int e = it & (sz - 1);
-                        float a, b;
-                        if (d + 1 == n) {
-                            a = chan[e];
-                            b = chan[e + sz];
-                        } else {
-                            const int src = (d == top) ? __shfl(myp, slot, 64) : slot;
-                            if (d + 1 < gl) {
-                                const float* p = slam + src * SL + (2 << d);
-                                a = p[e];
-                                b = p[e + sz];
+                    // four items per lane per pass: all loads issued before any use
+                    for (int it0 = lane; it0 < items; it0 += 256) {
+                        float a[4], b[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int it = it0 + 64 * u;
+                            const int slot = (it < items ? it : it0) >> d;
+                            const int e = it & (sz - 1);
+                            if (d + 1 == n) {
+                                a[u] = chan[e];
+                                b[u] = chan[e + sz];
                             } else {
-                                const float* p = glam + (size_t)src * N + (2 << d);
-                                a = p[e];
-                                b = p[e + sz];
+                                const int src = (d == top) ? __shfl(myp, slot, 64) : slot;
+                                if (it < items) {
+                                    if (d + 1 < gl) {
+                                        const float* p = slam + src * SL + ((2 << d) - BS);
+                                        a[u] = p[e];
+                                        b[u] = p[e + sz];
+                                    } else {
+                                        const float* p = glam + (size_t)src * N + (2 << d);
+                                        a[u] = p[e];
+                                        b[u] = p[e + sz];
+                                    }
+                                }
                             }
                         }
-                        float val;
+                        uint32_t w[4];
                         if (d == top && j != 0) {
-                            const int pss = __shfl(mypp, slot, 64);
-                            const uint32_t w = psw[pss * PW + ps_off(d) + (e >> 5)];
-                            val = ((w >> (e & 31)) & 1u) ? b - a : b + a;
-                        } else {
-                            val = g_ms(a, b);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int it = it0 + 64 * u;
+                                const int slot = (it < items ? it : it0) >> d;
+                                const int e = it & (sz - 1);
+                                const int pss = __shfl(mypp, slot, 64);
+                                w[u] = it < items ? psw[pss * PW + ps_off(d) + (e >> 5)] : 0u;
+                            }
                         }
-                        if (d < gl) slam[slot * SL + sz + e] = val;
-                        else glam[(size_t)slot * N + sz + e] = val;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int it = it0 + 64 * u;
+                            if (it >= items) continue;
+                            const int slot = it >> d;
+                            const int e = it & (sz - 1);
+                            float val;
+                            if (d == top && j != 0)
+                                val = ((w[u] >> (e & 31)) & 1u) ? b[u] - a[u] : b[u] + a[u];
+                            else
+                                val = g_ms(a[u], b[u]);
+                            if (d < gl) slam[slot * SL + sz - BS + e] = val;
+                            else glam[(size_t)slot * N + sz + e] = val;
+                        }
                     }
                     if (d < gl) wave_mem_order(); else wg_mem_order();
                     if (lane < act) set_byte(ptrL, d, lane);
@@ -233,7 +270,7 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
                             for (int e = 0; e < BS; ++e) src[e] = chan[e];
                         } else {
                             const int sl = (r == 0) ? lane : get_byte(ptrL, BL);
-                            const float* p = slam + sl * SL + BS;
+                            const float* p = slam + sl * SL;
 #pragma unroll
                             for (int e4 = 0; e4 < BS / 4; ++e4) {
                                 const float4 t4 = reinterpret_cast<const float4*>(p)[e4];
@@ -282,30 +319,22 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
                     const uint32_t cb = (uint32_t)(c & 1);
                     const uint32_t syn_i = code.syn[i];
                     // pull the parent's state: metric, syndrome, pointers, live registers
-                    const float nm = __shfl(met, c, 64);
-                    const uint32_t ns = __shfl(SYN, par, 64) ^ (cb ? syn_i : 0u);
-                    PtrVec nL, nP;
-                    nL.lo = shfl64(ptrL.lo, par);
-                    nL.hi = shfl64(ptrL.hi, par);
-                    nP.lo = shfl64(ptrP.lo, par);
-                    nP.hi = shfl64(ptrP.hi, par);
-                    uint32_t nps[5];
+                    // (lanes past the new list size pull lane 0's state, which no one reads)
+                    PM = __shfl(met, c, 64);
+                    SYN = __shfl(SYN, par, 64) ^ (cb ? syn_i : 0u);
+                    ptrL.lo = shfl64(ptrL.lo, par);
+                    ptrL.hi = shfl64(ptrL.hi, par);
+                    ptrP.lo = shfl64(ptrP.lo, par);
+                    ptrP.hi = shfl64(ptrP.hi, par);
 #pragma unroll
-                    for (int d = 0; d < BL; ++d) nps[d] = __shfl(ps[d], par, 64);
-                    float nlv[32];
+                    for (int d = 0; d < BL; ++d) ps[d] = __shfl(ps[d], par, 64);
 #pragma unroll
-                    for (int e = live_from; e < BS; ++e) nlv[e] = __shfl(lv[e], par, 64);
+                    for (int e = live_from; e < BS; ++e) lv[e] = __shfl(lv[e], par, 64);
                     if (lane < nact) {
-                        PM = nm;
-                        SYN = ns;
-                        ptrL = nL;
-                        ptrP = nP;
-#pragma unroll
-                        for (int d = 0; d < BL; ++d) ps[d] = nps[d];
-#pragma unroll
-                        for (int e = live_from; e < BS; ++e) lv[e] = nlv[e];
                         bit = cb;
-                        tbk[infoq * L + lane] = (uint8_t)(par | (cb << 7));
+                        const uint8_t tv = (uint8_t)(par | (cb << 7));
+                        if (tbg) tbg[infoq * L + lane] = tv;
+                        else tbk[infoq * L + lane] = tv;
                     }
                     act = nact;
                     ++infoq;
@@ -355,12 +384,34 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
         for (int it = lane; it < N; it += 64) dec[it] = 0;
         wave_mem_order();
         // ---------------- trace the chosen path back through the information bits
-        if (lane == 0) {
+        if (!tbg) {
+            if (lane == 0) {
+                int s = best;
+                for (int qq = infoq - 1; qq >= 0; --qq) {
+                    const uint8_t e = tbk[qq * L + s];
+                    dec[code.info_pos[qq]] = e >> 7;
+                    s = e & 0x7F;
+                }
+            }
+        } else {
+            // chunks of the global trace, last first, staged behind dec[] in LDS
+            uint8_t* ch = dec + ((N + 15) & ~15);
+            const int C = lay.tchunk;
             int s = best;
-            for (int qq = infoq - 1; qq >= 0; --qq) {
-                const uint8_t e = tbk[qq * L + s];
-                dec[code.info_pos[qq]] = e >> 7;
-                s = e & 0x7F;
+            wg_mem_order();
+            for (int q1 = infoq; q1 > 0; q1 -= C) {
+                const int q0 = q1 > C ? q1 - C : 0;
+                const int nb = (q1 - q0) * L;
+                for (int it = lane; it < nb; it += 64) ch[it] = tbg[(size_t)q0 * L + it];
+                wave_mem_order();
+                if (lane == 0) {
+                    for (int qq = q1 - 1; qq >= q0; --qq) {
+                        const uint8_t e = ch[(qq - q0) * L + s];
+                        dec[code.info_pos[qq]] = e >> 7;
+                        s = e & 0x7F;
+                    }
+                }
+                wave_mem_order();
             }
         }
         wave_mem_order();
@@ -374,7 +425,7 @@ __global__ __launch_bounds__(64) void scl_kernel(CodeDev code, const float* __re
 }
 
 using KernelFn = void (*)(CodeDev, const float*, const int32_t*, const int32_t*, int64_t, uint8_t*, uint8_t*,
-                          float*, float*, Layout);
+                          float*, unsigned char*, Layout);
 
 template <int L>
 KernelFn pick_bl(int bl) {
@@ -401,40 +452,86 @@ KernelFn pick(int L, int n) {
 
 int ps_words(int n) { return n <= 5 ? 1 : (1 << (n - 5)) - 1; }
 
-size_t lds_bytes(int L, int N, int n, int k, int gl) {
-    const size_t sl = (size_t(1) << gl) + 4;
-    size_t b = 0;
-    b += (size_t)L * sl * 4;           // LLR heap (levels BL..gl-1 used)
-    b += (size_t)L * ps_words(n) * 4;  // partial sums of levels >= 5
-    b += 64 * 4;                       // candidate metrics
-    b += (size_t)L * 4;                // inverse permutation
-    b += (size_t)k * L;                // trace
-    b = b > (size_t)N ? b : (size_t)N;  // the decoded bits reuse the space
-    return align_up(b, 16);
+// LDS floats per slot of the LLR heap: levels BL..gl-1 (level d at 2^d - 2^BL)
+int slot_floats(int n, int gl) {
+    const int bl = n < 5 ? n : 5;
+    return (gl > bl ? (1 << gl) - (1 << bl) : 0) + 4;
+}
+
+struct LdsPlan {
+    size_t bytes;
+    int tboff;   // LDS trace offset (tg == 0)
+    int tchunk;  // read-back chunk in information bits (tg == 1)
+};
+
+LdsPlan lds_plan(int L, int N, int n, int k, int gl, bool tg) {
+    LdsPlan p{};
+    size_t b = (size_t)L * slot_floats(n, gl) * 4;  // LLR heap
+    b += (size_t)L * ps_words(n) * 4;                // partial sums of levels >= 5
+    b += 64 * 4;                                      // candidate metrics
+    b += (size_t)L * 4;                               // inverse permutation
+    const size_t dec_end = align_up((size_t)N, 16);   // dec[] reuses the space from 0
+    if (!tg) {
+        b = align_up(b > dec_end ? b : dec_end, 16);
+        p.tboff = (int)b;
+        b += (size_t)k * L;                           // trace
+        p.bytes = align_up(b, 16);
+        p.tchunk = 0;
+    } else {
+        const int cmin = k < 64 ? k : 64;
+        const size_t need = dec_end + (size_t)cmin * L;
+        b = align_up(b > need ? b : need, 16);
+        p.bytes = b;
+        p.tboff = 0;
+        p.tchunk = (int)((b - dec_end) / L);
+    }
+    return p;
 }
 
 }  // namespace scl
 
-static size_t g_scl_lds_budget = 40 * 1024;
+// LDS per workgroup; 0 (automatic) divides a CU's 160 KB among as many
+// one-wave workgroups as the kernel's registers allow on a CU
+static std::atomic<int64_t> g_scl_lds_budget{0};
+constexpr size_t kLdsPerCu = 160 * 1024;
 
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan) {
     const int n = code->n, N = code->N, k = code->k;
     scl::KernelFn fn = scl::pick(L, n);
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
     const int gl_min = n < 6 ? n : 6;
+    // everything in LDS if it fits; otherwise the trace goes to the global
+    // slice first (written once per bit, read once), then the largest levels
+    bool tg = false;
     int gl = n;
-    while (gl > gl_min && scl::lds_bytes(L, N, n, k, gl) > g_scl_lds_budget) --gl;
-    size_t lds = scl::lds_bytes(L, N, n, k, gl);
-    if (lds > 160 * 1024) return set_error(POLAR_ERR_UNSUPPORTED, "scl: list too large for LDS");
+    scl::LdsPlan lp = scl::lds_plan(L, N, n, k, gl, tg);
+    size_t budget = (size_t)g_scl_lds_budget.load(std::memory_order_relaxed);
+    if (budget == 0) {
+        int by_regs = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, fn, 64, 0) != hipSuccess || by_regs < 1) by_regs = 1;
+        budget = (kLdsPerCu / (size_t)by_regs) & ~(size_t)255;
+        if (budget < 4096) budget = 4096;
+    }
+    if (lp.bytes > budget) {
+        tg = true;
+        while (gl > gl_min && scl::lds_plan(L, N, n, k, gl, tg).bytes > budget) --gl;
+        lp = scl::lds_plan(L, N, n, k, gl, tg);
+    }
+    if (lp.bytes > 160 * 1024) return set_error(POLAR_ERR_UNSUPPORTED, "scl: list too large for LDS");
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lp.bytes);
     if (e != hipSuccess || per_cu <= 0) per_cu = 1;
     int64_t grid = (int64_t)device_cu_count() * per_cu;
     if (max_frames < grid) grid = max_frames;
     if (grid < 1) grid = 1;
     plan->gl = gl;
-    plan->lds_bytes = lds;
-    plan->glob_per_wg = (gl < n) ? (size_t)L * N * 4 : 0;
+    plan->lds_bytes = lp.bytes;
+    plan->trace_glob = tg ? 1 : 0;
+    plan->trace_chunk = lp.tchunk;
+    plan->tb_off = lp.tboff;
+    const size_t lam_b = (gl < n) ? (size_t)L * N * 4 : 0;
+    plan->trace_off = lam_b;
+    plan->glob_per_wg = align_up(lam_b + (tg ? (size_t)k * L : 0), 256);
     plan->grid = (int)grid;
     return POLAR_OK;
 }
@@ -445,11 +542,16 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
     scl::KernelFn fn = scl::pick(L, code->n);
     scl::Layout lay;
     lay.gl = plan.gl;
-    lay.sl = (1 << plan.gl) + 4;
+    lay.sl = scl::slot_floats(code->n, plan.gl);
     lay.pw = scl::ps_words(code->n);
-    float* glam = plan.glob_per_wg ? reinterpret_cast<float*>(glob) : nullptr;
+    lay.tg = plan.trace_glob;
+    lay.tchunk = plan.trace_chunk;
+    lay.gbytes = (int64_t)plan.glob_per_wg;
+    lay.toff = (int64_t)plan.trace_off;
+    lay.tboff = plan.tb_off;
+    unsigned char* gb = plan.glob_per_wg ? reinterpret_cast<unsigned char*>(glob) : nullptr;
     hipLaunchKernelGGL(fn, dim3(plan.grid), dim3(64), plan.lds_bytes, stream, code->dev(), llr, frame_ids,
-                       count_dev, count_host, u_hat, crc_ok, pm, glam, lay);
+                       count_dev, count_host, u_hat, crc_ok, pm, gb, lay);
     return hip_check(hipGetLastError(), "scl_kernel launch");
 }
 
@@ -472,3 +574,12 @@ extern "C" polar_status scl_decode_batch(const polar_code* code, const float* ll
     st = launch_scl(code, plan, llr, L, frame_ids, nullptr, B, u_hat, crc_ok, pm, ws, stream);
     return st == POLAR_OK ? ok_status() : st;
 }
+
+extern "C" polar_status polar_set_scl_lds_budget(int64_t bytes) {
+    if (bytes != 0 && (bytes < 4096 || bytes > 160 * 1024))
+        return set_error(POLAR_ERR_INVALID_ARG, "polar_set_scl_lds_budget: bytes must be 0 or in [4096, 163840]");
+    g_scl_lds_budget.store(bytes, std::memory_order_relaxed);
+    return ok_status();
+}
+
+extern "C" int64_t polar_get_scl_lds_budget(void) { return g_scl_lds_budget.load(std::memory_order_relaxed); }

@@ -97,6 +97,49 @@ def train(N=256, K=128, crc_bits=8, T=10, frames=1_000_000, batch=4096, lr=1e-3,
     return tr, hist
 
 
+def bp_fail_rate(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int, stop: int = 1, out=None) -> float:
+    """Fraction of frames whose weighted BP verdict (re-encoding check and CRC)
+    is not ok after at most T iterations: the frames a hybrid hands to SCL."""
+    o = PB.bp_decode_batch(code, llr, max_iter=T, stop=stop, weights=W, out=out)
+    return 1.0 - float(o["ok"].float().mean())
+
+
+def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None):
+    """Normalized min-sum: the single weight alpha (every g term scaled by it)
+    with the fewest BP failures on the frames `llr`; returns (W, alpha, rate)."""
+    grid = grid if grid is not None else [0.86 + 0.01 * i for i in range(15)]
+    shape = (T, 2, code.n, code.N)
+    best = None
+    for a in grid:
+        W = torch.full(shape, float(a), dtype=torch.float32, device=llr.device)
+        r = bp_fail_rate(code, llr, W, T)
+        if best is None or r < best[2]:
+            best = (W, float(a), r)
+    return best
+
+
+def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factors=(0.96, 0.98, 1.02, 1.04),
+                  sweeps: int = 1):
+    """Coordinate search on the BP failure rate itself: each block of weights
+    (one iteration, one sweep direction) in turn is scaled by the factor that
+    lowers the failure rate on `llr` most, if any does.  Returns (W, rate)."""
+    T = W.shape[0]
+    cur = bp_fail_rate(code, llr, W, T)
+    for _ in range(sweeps):
+        for t in range(T):
+            for d in range(2):
+                base = W[t, d].clone()
+                best_f, best_r = None, cur
+                for f in factors:
+                    W[t, d] = base * f
+                    r = bp_fail_rate(code, llr, W, T)
+                    if r < best_r:
+                        best_f, best_r = f, r
+                W[t, d] = base if best_f is None else base * best_f
+                cur = best_r
+    return W, cur
+
+
 def info_of(code: PB.PolarCode, u_hat: torch.Tensor) -> torch.Tensor:
     """Information bits of decoded u vectors: the first K non-frozen positions
     (the CRC occupies the last c)."""

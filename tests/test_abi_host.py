@@ -63,6 +63,18 @@ def test_decoders_reject_null_code_without_device_work():
     assert lib.polar_encode(None, None, 0, None, None, None) == 1
 
 
+def test_scl_lds_budget_setter():
+    lib = PB.lib()
+    assert PB.polar_get_scl_lds_budget() == 0
+    assert lib.polar_set_scl_lds_budget(100) == 1
+    assert lib.polar_set_scl_lds_budget(200 * 1024) == 1
+    assert PB.polar_get_scl_lds_budget() == 0
+    PB.polar_set_scl_lds_budget(12288)
+    assert PB.polar_get_scl_lds_budget() == 12288
+    PB.polar_set_scl_lds_budget(0)
+    assert PB.polar_get_scl_lds_budget() == 0
+
+
 def test_bp_variants_query():
     assert PB.polar_bp_variants(1024) == [2, 3]
     assert PB.polar_bp_variants(8) == [2, 3]

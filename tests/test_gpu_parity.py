@@ -156,6 +156,25 @@ def test_scl_bit_exact_vs_f32_oracle(N, K, c, L):
     assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
 
 
+@pytest.mark.parametrize("budget", [4096, 8192, 65536, 163840])
+@pytest.mark.parametrize("N,K,c,L", [(64, 24, 8, 4), (256, 120, 8, 32), (1024, 512, 24, 32), (2048, 1024, 16, 8)])
+def test_scl_lds_budgets_bit_exact(N, K, c, L, budget):
+    """Every split of the list decoder's state between LDS and the global
+    slice (trace and upper tree levels) decodes identically."""
+    B = 9
+    code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, B, seed=3 * N + L)
+    ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32")
+    PB.polar_set_scl_lds_budget(budget)
+    try:
+        out = PB.scl_decode_batch(code, dev(llr), L)
+        uh, ok, pm = host(out["u_hat"]), host(out["crc_ok"]), host(out["pm"])
+    finally:
+        PB.polar_set_scl_lds_budget(0)
+    assert np.array_equal(ok, ref["crc_ok"])
+    assert np.array_equal(pm, ref["pm"].astype(np.float32))
+    assert np.array_equal(uh, ref["u_hat"])
+
+
 def test_scl_frame_subset_scatters_rows():
     N, K, c, L = 256, 120, 8, 4
     code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, 20, seed=9)
