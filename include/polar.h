@@ -191,6 +191,28 @@ polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64
                                  uint8_t* used_scl, int64_t* stats, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Pipelined hybrid over a sequence of batches: the asynchronous BP / SCL
+ * scheduling of Sec. III (Fig. 3) on two streams.  For batch j, BP and the
+ * compaction of its failed frames run on stream_bp; its CA-SCL and the merge
+ * run on stream_scl once they are done, so the list decoding of batch j
+ * overlaps the BP of batch j + 1.  Per-batch state is double buffered in the
+ * workspace (batch j + 2 waits for the merge of batch j); the list decoder's
+ * global slice is shared, since list decodes follow one another on stream_scl.
+ * llr, info_hat, used_scl: host arrays of nbatch device pointers ([B][N],
+ * [B][K], [B]; used_scl may be NULL or hold NULL entries); batches may share
+ * an input buffer.  Results and stats (accumulated as in hybrid_decode_batch)
+ * are complete when work enqueued on stream_bp after the call completes:
+ * stream_bp finally waits for stream_scl.  The two streams must differ.
+ * ws: at least polar_pipeline_workspace_size(code, B, L, params) bytes.
+ * ------------------------------------------------------------------------- */
+polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, const float* const* llr, int64_t B,
+                                     const bp_params* params, int32_t L, uint8_t* const* info_hat,
+                                     uint8_t* const* used_scl, int64_t* stats, void* ws, size_t ws_bytes,
+                                     hipStream_t stream_bp, hipStream_t stream_scl);
+polar_status polar_pipeline_workspace_size(const polar_code* code, int64_t B, int32_t L, const bp_params* params,
+                                           size_t* bytes);
+
 /* Workspace bytes needed by scl_decode_batch (params == NULL) or
  * hybrid_decode_batch (params != NULL) for B frames and list size L. */
 polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,

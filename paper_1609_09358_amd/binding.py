@@ -66,6 +66,8 @@ def lib():
             "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp, vp],
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "polar_set_scl_lds_budget": [i64],
+            "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
+            "polar_pipeline_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -278,6 +280,56 @@ def hybrid_decode_batch(code: PolarCode, llr: torch.Tensor, params: bp_params, L
     return out
 
 
+def polar_pipeline_workspace_size(code: PolarCode, B, L, params: bp_params) -> int:
+    s = C.c_size_t()
+    _check(lib().polar_pipeline_workspace_size(code.handle, B, L, C.byref(params), C.byref(s)))
+    return s.value
+
+
+class HybridPipeline:
+    """hybrid_decode_pipelined (BP on the current stream, CA-SCL and merge on a
+    second stream of default priority) with its workspace kept between calls."""
+
+    def __init__(self, code: PolarCode, max_iter=200, L=8, stop=1, llr_max=20.0, weights=None, variant=0):
+        self.code, self.L = code, L
+        self.weights = weights
+        self.params = make_bp_params(max_iter, stop, llr_max, weights, variant)
+        self.workspace = None
+        self.scl_stream = torch.cuda.Stream()
+
+    def __call__(self, llrs, outs=None, stats=None, want_used=False):
+        """Decode the batches `llrs` (a list of [B][N] tensors of one shape, which
+        may repeat); returns one dict(info[, used_scl]) per batch."""
+        code = self.code
+        nb = len(llrs)
+        if nb == 0:
+            return []
+        B = llrs[0].shape[0]
+        for t in llrs:
+            _dev(t, torch.float32, (B, code.N), "llr")
+        dev = llrs[0].device
+        if outs is None:
+            outs = []
+            for _ in range(nb):
+                o = dict(info=torch.empty((B, code.K), dtype=torch.uint8, device=dev))
+                if want_used:
+                    o["used_scl"] = torch.empty(B, dtype=torch.uint8, device=dev)
+                outs.append(o)
+        if stats is not None:
+            _dev(stats, torch.int64, (8,), "stats")
+        need = polar_pipeline_workspace_size(code, B, self.L, self.params)
+        if self.workspace is None or self.workspace.numel() < need:
+            self.workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        arr = C.c_void_p * nb
+        llr_a = arr(*[t.data_ptr() for t in llrs])
+        info_a = arr(*[o["info"].data_ptr() for o in outs])
+        used_a = arr(*[o["used_scl"].data_ptr() for o in outs]) if all("used_scl" in o for o in outs) else None
+        _check(lib().hybrid_decode_pipelined(code.handle, nb, llr_a, B, C.byref(self.params), self.L, info_a, used_a,
+                                             _ptr(stats), _ptr(self.workspace), self.workspace.numel(), _stream(),
+                                             C.c_void_p(self.scl_stream.cuda_stream)))
+        return outs
+
+
 # --------------------------------------------------------------------------- weighted (learned) BP
 
 def wbp_forward(code: PolarCode, llr, W, llr_max=20.0, variant=0, save=False, out=None):
@@ -358,4 +410,5 @@ class WeightedBPLoss(torch.autograd.Function):
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
-            "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget"]
+            "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
+            "hybrid_decode_pipelined", "polar_pipeline_workspace_size"]

@@ -88,9 +88,8 @@ struct HybridWs {
     size_t total;
 };
 
-HybridWs carve(const polar_code* code, int64_t B, const SclPlan& plan, void* base) {
-    HybridWs w{};
-    size_t off = 0;
+// per-batch state of B frames from `off`; returns the end offset
+size_t carve_batch(const polar_code* code, int64_t B, size_t off, char* base, HybridWs* w) {
     auto take = [&](size_t bytes) {
         size_t o = off;
         off = align_up(off + bytes, 256);
@@ -102,19 +101,72 @@ HybridWs carve(const polar_code* code, int64_t B, const SclPlan& plan, void* bas
     const size_t o_q = take((size_t)B * 4);
     const size_t o_c = take(4);
     const size_t o_s = take((size_t)B);
-    const size_t o_g = take(plan.glob_per_wg * plan.grid);
-    w.total = off;
     if (base) {
-        char* b = static_cast<char*>(base);
-        w.u_hat = reinterpret_cast<uint8_t*>(b + o_u);
-        w.ok = reinterpret_cast<uint8_t*>(b + o_ok);
-        w.iters = reinterpret_cast<int32_t*>(b + o_it);
-        w.queue = reinterpret_cast<int32_t*>(b + o_q);
-        w.count = reinterpret_cast<int32_t*>(b + o_c);
-        w.scl_ok = reinterpret_cast<uint8_t*>(b + o_s);
-        w.scl_glob = plan.glob_per_wg ? (void*)(b + o_g) : nullptr;
+        w->u_hat = reinterpret_cast<uint8_t*>(base + o_u);
+        w->ok = reinterpret_cast<uint8_t*>(base + o_ok);
+        w->iters = reinterpret_cast<int32_t*>(base + o_it);
+        w->queue = reinterpret_cast<int32_t*>(base + o_q);
+        w->count = reinterpret_cast<int32_t*>(base + o_c);
+        w->scl_ok = reinterpret_cast<uint8_t*>(base + o_s);
     }
-    return w;
+    return off;
+}
+
+// `slots` copies of the per-batch state followed by one list-decoder slice
+size_t carve(const polar_code* code, int64_t B, const SclPlan& plan, void* base, HybridWs* w, int slots) {
+    char* b = static_cast<char*>(base);
+    size_t off = 0;
+    for (int s = 0; s < slots; ++s) off = carve_batch(code, B, off, b, w ? &w[s] : nullptr);
+    const size_t o_g = off;
+    off = align_up(off + plan.glob_per_wg * plan.grid, 256);
+    if (b && w)
+        for (int s = 0; s < slots; ++s) {
+            w[s].scl_glob = plan.glob_per_wg ? (void*)(b + o_g) : nullptr;
+            w[s].total = off;
+        }
+    return off;
+}
+
+// four events (BP done and SCL done, per slot) of the calling thread on the
+// current device, created on first use and kept: a later call re-records them
+// after every wait that an earlier call enqueued on them
+polar_status pipeline_events(hipEvent_t** out) {
+    constexpr int kMaxDev = 64;
+    thread_local hipEvent_t ev[kMaxDev][4] = {};
+    int dev = 0;
+    polar_status st = hip_check(hipGetDevice(&dev), "get device");
+    if (st != POLAR_OK) return st;
+    if (dev < 0 || dev >= kMaxDev) return set_error(POLAR_ERR_UNSUPPORTED, "device index out of range");
+    for (int i = 0; i < 4; ++i)
+        if (!ev[dev][i] &&
+            (st = hip_check(hipEventCreateWithFlags(&ev[dev][i], hipEventDisableTiming), "event create")) != POLAR_OK)
+            return st;
+    *out = ev[dev];
+    return POLAR_OK;
+}
+
+// BP and compaction of one batch on `stream`
+polar_status enqueue_bp_part(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
+                             const HybridWs& w, hipStream_t stream) {
+    polar_status st = launch_bp(code, llr, B, p, w.u_hat, nullptr, w.iters, w.ok, stream);
+    if (st != POLAR_OK) return st;
+    hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, stream, w.count);
+    const unsigned cblocks = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(compact_kernel, dim3(cblocks), dim3(256), 0, stream, w.ok, B, w.queue, w.count);
+    return hip_check(hipGetLastError(), "compact launch");
+}
+
+// CA-SCL on the queued frames and the merge, on `stream`
+polar_status enqueue_scl_part(const polar_code* code, const SclPlan& plan, const float* llr, int64_t B, int L,
+                              const HybridWs& w, uint8_t* info_hat, uint8_t* used_scl, int64_t* stats,
+                              hipStream_t stream) {
+    polar_status st = launch_scl(code, plan, llr, L, w.queue, w.count, 0, w.u_hat, w.scl_ok, nullptr, w.scl_glob,
+                                 stream);
+    if (st != POLAR_OK) return st;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((B + kMergeFrames - 1) / kMergeFrames)), dim3(256), 0, stream,
+                       code->dev(), w.u_hat, w.ok, w.iters, w.scl_ok, B, info_hat, used_scl,
+                       reinterpret_cast<unsigned long long*>(stats));
+    return hip_check(hipGetLastError(), "merge launch");
 }
 
 }  // namespace
@@ -140,11 +192,18 @@ extern "C" polar_status polar_workspace_size(const polar_code* code, int64_t B, 
     SclPlan plan;
     polar_status st = scl_plan(code, L, B > 0 ? B : 1, &plan);
     if (st != POLAR_OK) return st;
-    if (!params) {
-        *bytes = plan.glob_per_wg * plan.grid;
-    } else {
-        *bytes = carve(code, B, plan, nullptr).total;
-    }
+    *bytes = params ? carve(code, B, plan, nullptr, nullptr, 1) : plan.glob_per_wg * plan.grid;
+    return ok_status();
+}
+
+extern "C" polar_status polar_pipeline_workspace_size(const polar_code* code, int64_t B, int32_t L,
+                                                      const bp_params* params, size_t* bytes) {
+    if (!code || !bytes || !params || B < 0)
+        return set_error(POLAR_ERR_INVALID_ARG, "polar_pipeline_workspace_size: bad argument");
+    SclPlan plan;
+    polar_status st = scl_plan(code, L, B > 0 ? B : 1, &plan);
+    if (st != POLAR_OK) return st;
+    *bytes = carve(code, B, plan, nullptr, nullptr, 2);
     return ok_status();
 }
 
@@ -158,20 +217,57 @@ extern "C" polar_status hybrid_decode_batch(const polar_code* code, const float*
     if (st != POLAR_OK) return st;
     SclPlan plan;
     if ((st = scl_plan(code, L, B > 0 ? B : 1, &plan)) != POLAR_OK) return st;
-    HybridWs w = carve(code, B, plan, nullptr);
-    if (!ws || ws_bytes < w.total) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_batch: workspace too small");
+    const size_t need = carve(code, B, plan, nullptr, nullptr, 1);
+    if (!ws || ws_bytes < need) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_batch: workspace too small");
     if (B == 0) return ok_status();
-    w = carve(code, B, plan, ws);
-    if ((st = launch_bp(code, llr, B, p, w.u_hat, nullptr, w.iters, w.ok, stream)) != POLAR_OK) return st;
-    hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, stream, w.count);
-    const unsigned cblocks = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(compact_kernel, dim3(cblocks), dim3(256), 0, stream, w.ok, B, w.queue, w.count);
-    if ((st = hip_check(hipGetLastError(), "compact launch")) != POLAR_OK) return st;
-    if ((st = launch_scl(code, plan, llr, L, w.queue, w.count, 0, w.u_hat, w.scl_ok, nullptr, w.scl_glob, stream)) !=
-        POLAR_OK)
-        return st;
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((B + kMergeFrames - 1) / kMergeFrames)), dim3(256), 0, stream, code->dev(), w.u_hat, w.ok, w.iters,
-                       w.scl_ok, B, info_hat, used_scl, reinterpret_cast<unsigned long long*>(stats));
-    if ((st = hip_check(hipGetLastError(), "merge launch")) != POLAR_OK) return st;
+    HybridWs w;
+    carve(code, B, plan, ws, &w, 1);
+    if ((st = enqueue_bp_part(code, llr, B, p, w, stream)) != POLAR_OK) return st;
+    if ((st = enqueue_scl_part(code, plan, llr, B, L, w, info_hat, used_scl, stats, stream)) != POLAR_OK) return st;
     return ok_status();
+}
+
+extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, const float* const* llr,
+                                                int64_t B, const bp_params* p, int32_t L, uint8_t* const* info_hat,
+                                                uint8_t* const* used_scl, int64_t* stats, void* ws, size_t ws_bytes,
+                                                hipStream_t stream_bp, hipStream_t stream_scl) {
+    if (!code || !p) return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_pipelined: null code or params");
+    if (nbatch < 0 || B < 0 || B > (int64_t)INT32_MAX)
+        return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_pipelined: bad batch count or size");
+    if (stream_bp == stream_scl) return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_pipelined: streams must differ");
+    if (nbatch > 0 && B > 0) {
+        if (!llr || !info_hat) return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_pipelined: null pointer array");
+        for (int64_t j = 0; j < nbatch; ++j)
+            if (!llr[j] || !info_hat[j]) return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_pipelined: null buffer");
+    }
+    polar_status st = check_bp_params(code, p);
+    if (st != POLAR_OK) return st;
+    SclPlan plan;
+    if ((st = scl_plan(code, L, B > 0 ? B : 1, &plan)) != POLAR_OK) return st;
+    const size_t need = carve(code, B, plan, nullptr, nullptr, 2);
+    if (!ws || ws_bytes < need) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_pipelined: workspace too small");
+    if (nbatch == 0 || B == 0) return ok_status();
+    HybridWs w[2];
+    carve(code, B, plan, ws, w, 2);
+    hipEvent_t* ev = nullptr;
+    if ((st = pipeline_events(&ev)) != POLAR_OK) return st;
+    hipEvent_t* bp_done = ev;
+    hipEvent_t* scl_done = ev + 2;
+    // the first batches must not start before work already queued on stream_scl
+    // has finished with the shared list-decoder slice of an earlier call
+    if (st == POLAR_OK) st = hip_check(hipEventRecord(scl_done[0], stream_scl), "event record");
+    if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[0], 0), "stream wait");
+    for (int64_t j = 0; j < nbatch && st == POLAR_OK; ++j) {
+        const int s = (int)(j & 1);
+        if (j >= 2) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[s], 0), "stream wait");
+        if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], stream_bp);
+        if (st == POLAR_OK) st = hip_check(hipEventRecord(bp_done[s], stream_bp), "event record");
+        if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_scl, bp_done[s], 0), "stream wait");
+        if (st == POLAR_OK)
+            st = enqueue_scl_part(code, plan, llr[j], B, L, w[s], info_hat[j], used_scl ? used_scl[j] : nullptr,
+                                  stats, stream_scl);
+        if (st == POLAR_OK) st = hip_check(hipEventRecord(scl_done[s], stream_scl), "event record");
+    }
+    if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[(nbatch - 1) & 1], 0), "stream wait");
+    return st == POLAR_OK ? ok_status() : st;
 }

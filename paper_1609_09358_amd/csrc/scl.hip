@@ -113,18 +113,29 @@ __device__ __forceinline__ uint32_t combine(uint32_t bit, const uint32_t (&ps)[5
 }
 
 // rank of this lane's candidate among the first ncand lanes under
-// (metric, lane); metrics are non-negative, so their bit patterns order them
+// (metric, lane); metrics are non-negative, so their bit patterns order them.
+// The metrics go through LDS once; each lane then reads them back as uint4
+// broadcasts, four at a time, so the reads overlap.
+template <int L>
 __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float met, int lane) {
+    constexpr int NC = 2 * L;
+    constexpr int G = NC / 4 < 1 ? 1 : (NC / 4 > 4 ? 4 : NC / 4);  // uint4 reads in flight
     if (lane < ncand) mets[lane] = __float_as_uint(met);
     wave_mem_order();
     const uint32_t mb = __float_as_uint(met);
     int rank = 0;
-    for (int c4 = 0; c4 < ncand; c4 += 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(mets + c4);
-        rank += (v.x < mb || (v.x == mb && c4 + 0 < lane)) ? 1 : 0;
-        rank += (c4 + 1 < ncand && (v.y < mb || (v.y == mb && c4 + 1 < lane))) ? 1 : 0;
-        rank += (c4 + 2 < ncand && (v.z < mb || (v.z == mb && c4 + 2 < lane))) ? 1 : 0;
-        rank += (c4 + 3 < ncand && (v.w < mb || (v.w == mb && c4 + 3 < lane))) ? 1 : 0;
+    for (int c0 = 0; c0 < ncand; c0 += 4 * G) {
+        uint4 v[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = reinterpret_cast<const uint4*>(mets + c0)[g];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = c0 + 4 * g;
+            rank += (c + 0 < ncand && (v[g].x < mb || (v[g].x == mb && c + 0 < lane))) ? 1 : 0;
+            rank += (c + 1 < ncand && (v[g].y < mb || (v[g].y == mb && c + 1 < lane))) ? 1 : 0;
+            rank += (c + 2 < ncand && (v[g].z < mb || (v[g].z == mb && c + 2 < lane))) ? 1 : 0;
+            rank += (c + 3 < ncand && (v[g].w < mb || (v[g].w == mb && c + 3 < lane))) ? 1 : 0;
+        }
     }
     return rank;
 }
@@ -156,7 +167,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     float* slam = reinterpret_cast<float*>(sm);                   // [L][SL]
     uint32_t* psw = reinterpret_cast<uint32_t*>(slam + L * SL);   // [L][PW]
     uint32_t* mets = psw + L * PW;                                // [64]
-    int32_t* inv = reinterpret_cast<int32_t*>(mets + 64);         // [L]
     uint8_t* tbk = sm + lay.tboff;                                // [k][L] unless tg
     uint8_t* dec = reinterpret_cast<uint8_t*>(slam);              // [N], reuses the LLR area at the end
 
@@ -310,11 +320,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     const float pmp = __shfl(PM, p, 64);
                     const float pen = (b != (lp < 0.0f ? 1 : 0)) ? fabsf(lp) : 0.0f;
                     const float met = pmp + pen;
-                    const int rank = candidate_rank(mets, ncand, met, lane);
+                    const int rank = candidate_rank<L>(mets, ncand, met, lane);
                     const int nact = ncand < L ? ncand : L;
-                    if (lane < ncand && rank < L) inv[rank] = lane;
-                    wave_mem_order();
-                    const int c = lane < nact ? inv[lane] : 0;
+                    // each candidate pushes its lane to the lane of its rank (ranks
+                    // are distinct; lanes without a candidate push to themselves,
+                    // above every rank), so lane l receives the candidate of rank l
+                    const int c = __builtin_amdgcn_ds_permute((lane < ncand ? rank : lane) << 2, lane);
                     const int par = c >> 1;
                     const uint32_t cb = (uint32_t)(c & 1);
                     const uint32_t syn_i = code.syn[i];
@@ -469,7 +480,6 @@ LdsPlan lds_plan(int L, int N, int n, int k, int gl, bool tg) {
     size_t b = (size_t)L * slot_floats(n, gl) * 4;  // LLR heap
     b += (size_t)L * ps_words(n) * 4;                // partial sums of levels >= 5
     b += 64 * 4;                                      // candidate metrics
-    b += (size_t)L * 4;                               // inverse permutation
     const size_t dec_end = align_up((size_t)N, 16);   // dec[] reuses the space from 0
     if (!tg) {
         b = align_up(b > dec_end ? b : dec_end, 16);

@@ -61,6 +61,8 @@ def test_decoders_reject_null_code_without_device_work():
     s = C.c_size_t()
     assert lib.polar_workspace_size(None, 1, 8, None, C.byref(s)) == 1
     assert lib.polar_encode(None, None, 0, None, None, None) == 1
+    assert lib.hybrid_decode_pipelined(None, 1, None, 1, C.byref(p), 8, None, None, None, None, 0, None, None) == 1
+    assert lib.polar_pipeline_workspace_size(None, 1, 8, C.byref(p), C.byref(s)) == 1
 
 
 def test_scl_lds_budget_setter():

@@ -9,6 +9,8 @@ are bit-exact against the oracle's float32 build (decisions taken in the
 paper's 32-bit precision on both sides, same operation order); soft outputs
 match the float64 build within |a - b| <= 1e-4 * max(1, |b|).
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -231,3 +233,58 @@ def test_hybrid_full_size_sampled():
     assert np.array_equal(used[pick], ref["used_scl"])
     fer = np.mean(np.any(info_hat != info, axis=1))
     assert fer < 0.05
+
+
+# ------------------------------------------------------------------ pipelined hybrid (two streams)
+
+@pytest.mark.parametrize("nb", [1, 2, 5])
+def test_pipelined_hybrid_matches_single_stream_and_oracle(nb):
+    """Batches decoded with the BP / SCL stages on two streams give, batch by
+    batch, the single-stream hybrid's output and the oracle's; statistics add up."""
+    N, K, c, L, it, B = 1024, 512, 16, 8, 40, 40
+    batches = [frames(N, K, c, 2.5, 1.5, B, seed=100 + j)[4] for j in range(nb)]
+    code = PB.PolarCode(N, K, c, 0, 2.5)
+    pipe = PB.HybridPipeline(code, max_iter=it, L=L)
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    outs = pipe([dev(b) for b in batches], stats=stats, want_used=True)
+    single = PB.HybridDecoder(code, max_iter=it, L=L)
+    tot = 0
+    for j, b in enumerate(batches):
+        ref = O.hybrid_batch(b, code.frozen, K, c, POLY[c], it, L, prec="f32")
+        one = single(dev(b))
+        assert np.array_equal(host(outs[j]["info"]), ref["info"])
+        assert np.array_equal(host(outs[j]["used_scl"]), ref["used_scl"])
+        assert np.array_equal(host(outs[j]["info"]), host(one["info"]))
+        tot += int(ref["used_scl"].sum())
+    st = host(stats)
+    assert st[0] == nb * B and st[2] == tot and tot > 0
+
+
+def test_pipelined_hybrid_repeated_input_and_reuse():
+    """One resident input decoded as many batches (as the benchmark does), twice
+    in a row with the same workspace, learned weights, list size 32."""
+    N, K, c, L, T, B = 1024, 512, 24, 32, 20, 300
+    code, info, u, x, llr = frames(N, K, c, 2.5, 2.0, B, seed=77)
+    W = torch.full((T, 2, 10, N), 0.94, device="cuda")
+    ref = PB.HybridDecoder(code, max_iter=T, L=L, weights=W)(dev(llr))
+    pipe = PB.HybridPipeline(code, max_iter=T, L=L, weights=W)
+    d = dev(llr)
+    for _ in range(2):
+        outs = pipe([d] * 7)
+        for o in outs:
+            assert torch.equal(o["info"], ref["info"])
+
+
+def test_pipelined_hybrid_edge_cases():
+    N, K, c = 256, 128, 8
+    code = PB.PolarCode(N, K, c, 0, 2.5)
+    pipe = PB.HybridPipeline(code, max_iter=10, L=4)
+    assert pipe([]) == []
+    empty = torch.empty((0, N), dtype=torch.float32, device="cuda")
+    outs = pipe([empty, empty])
+    assert outs[0]["info"].shape == (0, K)
+    p = PB.make_bp_params(10)
+    s = torch.cuda.current_stream().cuda_stream
+    arr = (C.c_void_p * 1)(empty.data_ptr())
+    assert PB.lib().hybrid_decode_pipelined(code.handle, 1, arr, 0, C.byref(p), 4, arr, None, None, None, 0,
+                                            C.c_void_p(s), C.c_void_p(s)) == 1
