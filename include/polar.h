@@ -213,6 +213,39 @@ polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, con
 polar_status polar_pipeline_workspace_size(const polar_code* code, int64_t B, int32_t L, const bp_params* params,
                                            size_t* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Ragged batches that mix several codes (block lengths and rates): the
+ * hybrid decoder of Sec. III applied frame by frame with each frame's code.
+ * A plan holds up to 16 codes (all of the current device), the BP parameters
+ * (unweighted; params->variant is replaced by variants[c] when variants is
+ * not NULL, 0 = default layout), the list size and its own device workspace
+ * for up to max_frames frames per call; creating it allocates, calls do not.
+ * A call decodes B frames in any order: frame f uses code code_of_frame[f]
+ * (frames with an id outside [0, n_codes) are skipped), its N LLRs start at
+ * element llr_off[f] of llr and its K information bits are written from
+ * element out_off[f] of info_hat (all dev; the caller keeps the offsets inside
+ * its buffers).  used_scl dev [B] or NULL; stats as in hybrid_decode_batch.
+ * On the device the frames are bucketed by code; each code's BP is a
+ * persistent kernel over its bucket that appends its failed frames to a queue
+ * drained by the code's persistent CA-SCL kernel; the codes' chains are
+ * concurrent branches on the plan's streams; a merge writes the results.
+ * polar_mixed_decode enqueues the kernels; polar_mixed_decode_graph replays
+ * the same work as one hipGraph, captured on its first call on the plan
+ * (the kernels read the per-call buffers through a device argument block
+ * that a one-thread kernel fills before the graph runs).  Results are
+ * complete when later work on `stream` runs.  One call at a time per plan.
+ * ------------------------------------------------------------------------- */
+typedef struct polar_mixed polar_mixed;
+polar_status polar_mixed_create(const polar_code* const* codes, int32_t n_codes, int64_t max_frames,
+                                const bp_params* params, int32_t L, const int32_t* variants, polar_mixed** out);
+polar_status polar_mixed_decode(polar_mixed* m, int64_t B, const float* llr, const int32_t* code_of_frame,
+                                const int64_t* llr_off, const int64_t* out_off, uint8_t* info_hat,
+                                uint8_t* used_scl, int64_t* stats, hipStream_t stream);
+polar_status polar_mixed_decode_graph(polar_mixed* m, int64_t B, const float* llr, const int32_t* code_of_frame,
+                                      const int64_t* llr_off, const int64_t* out_off, uint8_t* info_hat,
+                                      uint8_t* used_scl, int64_t* stats, hipStream_t stream);
+void polar_mixed_free(polar_mixed* m);
+
 /* Workspace bytes needed by scl_decode_batch (params == NULL) or
  * hybrid_decode_batch (params != NULL) for B frames and list size L. */
 polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,

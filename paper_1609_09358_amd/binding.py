@@ -68,6 +68,9 @@ def lib():
             "polar_set_scl_lds_budget": [i64],
             "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
             "polar_pipeline_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
+            "polar_mixed_create": [vp, i32, i64, C.POINTER(bp_params), i32, vp, C.POINTER(vp)],
+            "polar_mixed_decode": [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp],
+            "polar_mixed_decode_graph": [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -75,6 +78,8 @@ def lib():
             fn.restype = C.c_int
         L.polar_get_scl_lds_budget.argtypes = []
         L.polar_get_scl_lds_budget.restype = i64
+        L.polar_mixed_free.argtypes = [vp]
+        L.polar_mixed_free.restype = None
         L.polar_free_code.argtypes = [vp]
         L.polar_free_code.restype = None
         _lib = L
@@ -330,6 +335,52 @@ class HybridPipeline:
         return outs
 
 
+class MixedPlan:
+    """polar_mixed plan: hybrid decoding of ragged batches mixing several codes."""
+
+    def __init__(self, codes, max_frames, max_iter=200, L=8, stop=1, llr_max=20.0, variants=None):
+        self.codes = list(codes)
+        self.max_frames = int(max_frames)
+        self.params = make_bp_params(max_iter, stop, llr_max)
+        n = len(self.codes)
+        arr = (C.c_void_p * n)(*[c.handle.value for c in self.codes])
+        var = None if variants is None else (C.c_int32 * n)(*[int(v) for v in variants])
+        h = C.c_void_p()
+        _check(lib().polar_mixed_create(arr, n, self.max_frames, C.byref(self.params), int(L), var, C.byref(h)))
+        self.handle = h
+
+    def layout(self, code_of_frame):
+        """Row offsets of a ragged batch laid out densely in frame order:
+        (llr_off, out_off, total LLR elements, total information bits)."""
+        cf = np.asarray(code_of_frame)
+        Ns = np.array([c.N for c in self.codes], np.int64)[cf]
+        Ks = np.array([c.K for c in self.codes], np.int64)[cf]
+        llr_off = np.concatenate([[0], np.cumsum(Ns)[:-1]]).astype(np.int64)
+        out_off = np.concatenate([[0], np.cumsum(Ks)[:-1]]).astype(np.int64)
+        return llr_off, out_off, int(Ns.sum()), int(Ks.sum())
+
+    def __call__(self, llr, code_of_frame, llr_off, out_off, info_hat, used_scl=None, stats=None, graph=False):
+        B = int(code_of_frame.shape[0])
+        for t, dt, nm in ((code_of_frame, torch.int32, "code_of_frame"), (llr_off, torch.int64, "llr_off"),
+                          (out_off, torch.int64, "out_off")):
+            _dev(t, dt, (B,), nm)
+        _dev(llr, torch.float32, None, "llr")
+        _dev(info_hat, torch.uint8, None, "info_hat")
+        if used_scl is not None:
+            _dev(used_scl, torch.uint8, (B,), "used_scl")
+        if stats is not None:
+            _dev(stats, torch.int64, (8,), "stats")
+        fn = lib().polar_mixed_decode_graph if graph else lib().polar_mixed_decode
+        _check(fn(self.handle, B, _ptr(llr), _ptr(code_of_frame), _ptr(llr_off), _ptr(out_off), _ptr(info_hat),
+                  _ptr(used_scl), _ptr(stats), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.polar_mixed_free(h)
+            self.handle = None
+
+
 # --------------------------------------------------------------------------- weighted (learned) BP
 
 def wbp_forward(code: PolarCode, llr, W, llr_max=20.0, variant=0, save=False, out=None):
@@ -411,4 +462,5 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
-            "hybrid_decode_pipelined", "polar_pipeline_workspace_size"]
+            "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_mixed_create", "polar_mixed_decode",
+            "polar_mixed_decode_graph", "polar_mixed_free"]

@@ -93,28 +93,36 @@ __device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub
     return s == 0;
 }
 
-// SAVE (training): every message a column produces is also written to
-// saved[frame][iteration][direction][column][node], direction 0 = R (row s+1
-// of column s), 1 = L (row s), for the adjoint kernel.
-template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE>
-__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
-    CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
-    const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
-    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, float* __restrict__ saved) {
-    using G = Geom<NLOG, RLOG>;
-    constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
-    __shared__ float tb[G::TAB.words];
-    __shared__ __attribute__((aligned(16))) uint8_t ubytes[G::FPW * N];
-    __shared__ __attribute__((aligned(16))) uint8_t xbytes[G::FPW * N];
+// LDS of one workgroup: transpose buffers and the packed-decision staging
+template <class G>
+struct BpShared {
+    float tb[G::TAB.words];
+    __attribute__((aligned(16))) uint8_t ubytes[G::FPW * G::N];
+    __attribute__((aligned(16))) uint8_t xbytes[G::FPW * G::N];
+};
 
-    const int tid = threadIdx.x;
-    const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
-    const int slot = (G::T < 64) ? (tid >> G::P) : 0;
-    const int64_t frame = (int64_t)blockIdx.x * G::FPW + slot;
-    if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
-    const int lane = (G::T < 64) ? t : (tid & 63);
-    uint8_t* ub = ubytes + slot * N;
-    uint8_t* xb = xbytes + slot * N;
+// Where one frame's data lives.  SAVE (training): every message a column
+// produces is also written to sv[iteration][direction][column][node],
+// direction 0 = R (row s+1 of column s), 1 = L (row s), for the adjoint kernel.
+struct FrameIO {
+    const float* llr;   // [N] channel LLRs
+    uint8_t* u_hat;     // [N] or null
+    float* llr_u;       // [N] or null
+    int32_t* iters;     // one value or null
+    uint8_t* ok;        // one value or null
+    float* saved;       // SAVE only
+};
+
+// Decode one frame: thread t of the frame's T threads, frame slot `slot` of
+// its wavefront (T < 64) or workgroup.  Returns the verdict (for queues).
+template <class G, bool WEIGHTED, bool SAVE>
+__device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io, int max_iter, int stop, float lmax,
+                                         const float* __restrict__ W, BpShared<G>& sh, int t, int slot) {
+    constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
+    float* tb = sh.tb;
+    const int lane = (G::T < 64) ? t : (threadIdx.x & 63);
+    uint8_t* ub = sh.ubytes + slot * N;
+    uint8_t* xb = sh.xbytes + slot * N;
 
     // LDS bases of this thread for each boundary, on both sides
     int bfrom[G::NB > 0 ? G::NB : 1], bto[G::NB > 0 ? G::NB : 1];
@@ -136,7 +144,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
             Lm[s][v] = 0.0f;
             Rm[s][v] = 0.0f;
         }
-    const float* fl = llr + frame * N;
+    const float* fl = io.llr;
     {
         const int ib = idx_base<G, KL>(t);
 #pragma unroll
@@ -159,7 +167,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     float L0[V];
     while (true) {
         const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * N : nullptr;
-        float* Sit = SAVE ? saved + ((size_t)frame * max_iter + it) * 2 * n * N : nullptr;
+        float* Sit = SAVE ? io.saved + (size_t)it * 2 * n * N : nullptr;
         // ---------------- R sweep: columns 0..n-1
         static_for<0, G::NWIN>([&](auto KC) {
             constexpr int k = decltype(KC)::value;
@@ -281,23 +289,84 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     }
 
     // ---------------- outputs (window 0 layout: V consecutive nodes per thread)
+    const bool okv = stop == 2 ? cok : (gok && cok);
     {
         const int ib = idx_base<G, 0>(t);
-        if (u_hat) {
-            uint8_t* uo = u_hat + frame * N + ib;
+        if (io.u_hat) {
+            uint8_t* uo = io.u_hat + ib;
             const uint8_t* src = ub + ib;
 #pragma unroll
             for (int v = 0; v < V; ++v) uo[v] = src[v];
         }
-        if (llr_u) {
-            float* lo = llr_u + frame * N + ib;
+        if (io.llr_u) {
+            float* lo = io.llr_u + ib;
 #pragma unroll
             for (int v = 0; v < V; ++v) lo[v] = L0[v] + prior[v];
         }
         if (t == 0) {
-            if (iters_out) iters_out[frame] = it;
-            if (ok_out) ok_out[frame] = (uint8_t)(stop == 2 ? cok : (gok && cok));
+            if (io.iters) *io.iters = it;
+            if (io.ok) *io.ok = (uint8_t)okv;
         }
+    }
+    return okv;
+}
+
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE>
+__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
+    CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
+    const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
+    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, float* __restrict__ saved) {
+    using G = Geom<NLOG, RLOG>;
+    constexpr int N = G::N;
+    __shared__ BpShared<G> sh;
+    const int tid = threadIdx.x;
+    const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
+    const int slot = (G::T < 64) ? (tid >> G::P) : 0;
+    const int64_t frame = (int64_t)blockIdx.x * G::FPW + slot;
+    if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
+    FrameIO io;
+    io.llr = llr + frame * N;
+    io.u_hat = u_hat ? u_hat + frame * N : nullptr;
+    io.llr_u = llr_u ? llr_u + frame * N : nullptr;
+    io.iters = iters_out ? iters_out + frame : nullptr;
+    io.ok = ok_out ? ok_out + frame : nullptr;
+    io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
+    bp_frame<G, WEIGHTED, SAVE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+}
+
+// Persistent form for ragged batches: workgroups walk the list ids[0..*count)
+// (the count lives on the device); frame id's LLR row starts at element
+// io->off[id] of io->llr, its u_hat row at id * u_stride; iters and ok are
+// indexed by id; failed frames are appended to fail_ids (one atomic each).
+template <int NLOG, int RLOG, bool WEIGHTED>
+__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
+    CodeDev code, const MixedIo* __restrict__ mio, const int32_t* __restrict__ ids, const int32_t* __restrict__ count,
+    int max_iter, int stop, float lmax, const float* __restrict__ W, uint8_t* __restrict__ u_hat, int64_t u_stride,
+    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, int32_t* __restrict__ fail_ids,
+    int32_t* __restrict__ fail_count) {
+    using G = Geom<NLOG, RLOG>;
+    __shared__ BpShared<G> sh;
+    const int tid = threadIdx.x;
+    const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
+    const int slot = (G::T < 64) ? (tid >> G::P) : 0;
+    const int64_t cnt = *count;
+    const float* llr = mio->llr;
+    const int64_t* off = mio->off;
+    const int64_t stride = (int64_t)gridDim.x * G::FPW;
+    for (int64_t q0 = (int64_t)blockIdx.x * G::FPW; q0 < cnt; q0 += stride) {
+        const int64_t q = q0 + slot;
+        if (G::T >= 64) __syncthreads();  // the previous frame's staging is read
+        if (q >= cnt) break;             // only when T < 64: this slot's wavefront lanes leave alone
+        const int id = ids[q];
+        FrameIO io;
+        io.llr = llr + off[id];
+        io.u_hat = u_hat + (int64_t)id * u_stride;
+        io.llr_u = nullptr;
+        io.iters = iters_out + id;
+        io.ok = ok_out + id;
+        io.saved = nullptr;
+        const bool okv = bp_frame<G, WEIGHTED, false>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        if (t == 0 && !okv) fail_ids[atomicAdd(fail_count, 1)] = id;
     }
 }
 
@@ -306,15 +375,20 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
 using KernelFn = void (*)(CodeDev, const float*, int64_t, int, int, float, const float*, uint8_t*, float*,
                           int32_t*, uint8_t*, float*);
 
+using GatherFn = void (*)(CodeDev, const MixedIo*, const int32_t*, const int32_t*, int, int, float, const float*,
+                          uint8_t*, int64_t, int32_t*, uint8_t*, int32_t*, int32_t*);
+
 struct Entry {
     KernelFn plain, weighted, weighted_save;
+    GatherFn gather_plain, gather_weighted;
     int wg, fpw;
 };
 
 template <int NL, int RL>
 constexpr Entry make_entry() {
     return Entry{&bp_kernel<NL, RL, false, false>, &bp_kernel<NL, RL, true, false>, &bp_kernel<NL, RL, true, true>,
-                 Geom<NL, RL>::WG, Geom<NL, RL>::FPW};
+                 &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
+                 Geom<NL, RL>::FPW};
 }
 
 // variants: register bits r = 2 or 3 (variant id = r)
@@ -368,6 +442,32 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
                        p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
     return hip_check(hipGetLastError(), "bp_kernel launch");
+}
+
+polar_status bp_gather_grid(const polar_code* code, const bp_params* p, int64_t max_frames, int* grid) {
+    const int variant = p->variant ? p->variant : bp_default_variant(code->n);
+    const bp::Entry* e = bp::lookup(code->n, variant);
+    if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "bp: no kernel variant for this block length");
+    bp::GatherFn fn = p->weights ? e->gather_weighted : e->gather_plain;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, e->wg, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    int64_t g = (int64_t)device_cu_count() * per_cu;
+    const int64_t need = (max_frames + e->fpw - 1) / e->fpw;
+    if (need < g) g = need;
+    *grid = (int)(g < 1 ? 1 : g);
+    return POLAR_OK;
+}
+
+polar_status launch_bp_gather(const polar_code* code, const MixedIo* io, const int32_t* ids, const int32_t* count,
+                              const bp_params* p, uint8_t* u_hat, int64_t u_stride, int32_t* iters, uint8_t* ok,
+                              int32_t* fail_ids, int32_t* fail_count, int grid, hipStream_t stream) {
+    const int variant = p->variant ? p->variant : bp_default_variant(code->n);
+    const bp::Entry* e = bp::lookup(code->n, variant);
+    if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "bp: no kernel variant for this block length");
+    bp::GatherFn fn = p->weights ? e->gather_weighted : e->gather_plain;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(e->wg), 0, stream, code->dev(), io, ids, count, p->max_iter,
+                       p->stop, p->llr_max, p->weights, u_hat, u_stride, iters, ok, fail_ids, fail_count);
+    return hip_check(hipGetLastError(), "bp_gather_kernel launch");
 }
 
 polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,

@@ -66,6 +66,20 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
 polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,
                             const float* W, int variant, uint8_t* u_hat, float* llr_u, uint8_t* ok, float* saved,
                             hipStream_t stream);
+// Per-call inputs of a ragged batch, read by the kernels from device memory
+// (so a captured graph stays valid across calls with other buffers)
+struct MixedIo {
+    const float* llr;     // LLR rows
+    const int64_t* off;   // row of frame f starts at element off[f]
+};
+
+// persistent BP over a device list of frame ids with ragged row offsets;
+// failed frames are appended to fail_ids
+polar_status bp_gather_grid(const polar_code* code, const bp_params* p, int64_t max_frames, int* grid);
+// u_hat row of frame f: f * u_stride
+polar_status launch_bp_gather(const polar_code* code, const MixedIo* io, const int32_t* ids, const int32_t* count,
+                              const bp_params* p, uint8_t* u_hat, int64_t u_stride, int32_t* iters, uint8_t* ok,
+                              int32_t* fail_ids, int32_t* fail_count, int grid, hipStream_t stream);
 bool bp_variant_supported(int n, int variant);
 int bp_default_variant(int n);
 int bp_list_variants(int n, int32_t* ids, int cap);
@@ -81,10 +95,12 @@ struct SclPlan {
     int grid;            // workgroups launched
 };
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan);
+// io (optional): LLR rows of a ragged batch (frame f at element io->off[f]),
+// u_hat rows then at f * u_stride
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host,
                         uint8_t* u_hat, uint8_t* crc_ok, float* pm, void* glob,
-                        hipStream_t stream);
+                        hipStream_t stream, const MixedIo* io = nullptr, int64_t u_stride = 0);
 
 int device_cu_count();
 

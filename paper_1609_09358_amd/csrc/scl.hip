@@ -149,6 +149,7 @@ struct Layout {
     int64_t gbytes;  // bytes of the global slice per workgroup
     int64_t toff;    // byte offset of the trace inside the slice
     int tboff;       // byte offset of the LDS trace (at least N: dec[] sits below it)
+    int64_t u_stride;  // u_hat row stride of a ragged batch
 };
 
 template <int L, int BL>
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
                                                  uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                                                  float* __restrict__ pm_out, unsigned char* __restrict__ glob_all,
-                                                 Layout lay) {
+                                                 Layout lay, const MixedIo* __restrict__ mio) {
     constexpr int BS = 1 << BL;  // bits per block
     extern __shared__ __attribute__((aligned(16))) unsigned char sm[];
     const int lane = threadIdx.x;
@@ -175,9 +176,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     uint8_t* tbg = lay.tg ? gbase + lay.toff : nullptr;       // [k][L] when tg
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
+    const float* const llr_base = mio ? mio->llr : llr;
+    const int64_t* const row_off = mio ? mio->off : nullptr;
     for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
         const int64_t f = frame_ids ? (int64_t)frame_ids[q] : q;
-        const float* chan = llr + f * N;
+        // rows of frame f: LLRs at row_off[f] (ragged batch) or f * N; u_hat at
+        // f * u_stride (ragged batch) or f * N
+        const float* chan = llr_base + (row_off ? row_off[f] : f * N);
+        const int64_t urow = f * (row_off ? lay.u_stride : (int64_t)N);
 
         int act = 1;
         float PM = 0.0f;
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             }
         }
         wave_mem_order();
-        for (int it = lane; it < N; it += 64) u_hat[f * N + it] = dec[it];
+        for (int it = lane; it < N; it += 64) u_hat[urow + it] = dec[it];
         if (lane == 0) {
             crc_ok[f] = best_ok ? 1 : 0;
             if (pm_out) pm_out[f] = best_pm;
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
 }
 
 using KernelFn = void (*)(CodeDev, const float*, const int32_t*, const int32_t*, int64_t, uint8_t*, uint8_t*,
-                          float*, unsigned char*, Layout);
+                          float*, unsigned char*, Layout, const MixedIo*);
 
 template <int L>
 KernelFn pick_bl(int bl) {
@@ -548,7 +554,8 @@ polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan
 
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host, uint8_t* u_hat,
-                        uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream) {
+                        uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream, const MixedIo* io,
+                        int64_t u_stride) {
     scl::KernelFn fn = scl::pick(L, code->n);
     scl::Layout lay;
     lay.gl = plan.gl;
@@ -559,9 +566,10 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
     lay.gbytes = (int64_t)plan.glob_per_wg;
     lay.toff = (int64_t)plan.trace_off;
     lay.tboff = plan.tb_off;
+    lay.u_stride = u_stride;
     unsigned char* gb = plan.glob_per_wg ? reinterpret_cast<unsigned char*>(glob) : nullptr;
     hipLaunchKernelGGL(fn, dim3(plan.grid), dim3(64), plan.lds_bytes, stream, code->dev(), llr, frame_ids,
-                       count_dev, count_host, u_hat, crc_ok, pm, gb, lay);
+                       count_dev, count_host, u_hat, crc_ok, pm, gb, lay, io);
     return hip_check(hipGetLastError(), "scl_kernel launch");
 }
 

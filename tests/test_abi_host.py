@@ -63,6 +63,11 @@ def test_decoders_reject_null_code_without_device_work():
     assert lib.polar_encode(None, None, 0, None, None, None) == 1
     assert lib.hybrid_decode_pipelined(None, 1, None, 1, C.byref(p), 8, None, None, None, None, 0, None, None) == 1
     assert lib.polar_pipeline_workspace_size(None, 1, 8, C.byref(p), C.byref(s)) == 1
+    h = C.c_void_p()
+    assert lib.polar_mixed_create(None, 1, 16, C.byref(p), 8, None, C.byref(h)) == 1
+    assert lib.polar_mixed_decode(None, 0, None, None, None, None, None, None, None, None) == 1
+    assert lib.polar_mixed_decode_graph(None, 0, None, None, None, None, None, None, None, None) == 1
+    lib.polar_mixed_free(None)
 
 
 def test_scl_lds_budget_setter():
