@@ -288,6 +288,8 @@ def main():
         torch.cuda.synchronize()
         extra["copy_calibration_bytes"] = src.numel() * 4
 
+    extra["c3_mixed"] = c3_mixed(args.steps)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(info, z, sigma2, code.frozen, N, K, C, L, T, W.cpu().numpy().astype(np.float64),
@@ -318,6 +320,47 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line))
+
+
+def c3_mixed(steps, B=4096, max_iter=200, L=8):
+    """Ragged batch of twelve codes (N 256..2048, rates 1/4..3/4, CRC-16),
+    Eb/N0 uniform in [1, 3] dB per frame: autotuned plan, eager launches and
+    the replayed hipGraph, each timed over `steps` calls."""
+    import torch
+
+    from paper_1609_09358_amd import autotune
+    from paper_1609_09358_amd import binding as PB
+    from paper_1609_09358_amd import mixed_workload as MW
+
+    codes = MW.make_codes()
+    batch = MW.ragged_batch(codes, B, seed=3)
+    tuned = autotune.tune_mixed(codes, [rows for _, rows in batch["per_code"]], max_iter, L)
+    plan = PB.MixedPlan(codes, max_frames=B, max_iter=max_iter, L=L, variants=tuned["variants"])
+    info_hat = torch.empty(batch["total_info_bits"], dtype=torch.uint8, device="cuda")
+    used = torch.empty(B, dtype=torch.uint8, device="cuda")
+    args = (batch["llr"], batch["code_of_frame"], batch["llr_off"], batch["out_off"], info_hat, used)
+    res = {}
+    for graph in (False, True):
+        plan(*args, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan(*args, graph=graph)
+        torch.cuda.synchronize()
+        res["graph" if graph else "eager"] = (time.perf_counter() - t0) / steps
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    plan(*args, stats=stats, graph=True)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    fe = MW.frame_errors(batch, info_hat, codes)
+    PB.polar_set_scl_lds_budget(0)
+    bits = batch["total_info_bits"]
+    return {
+        "frames": B, "codes": len(codes), "info_bits": bits,
+        "eager_ms": round(res["eager"] * 1e3, 3), "graph_ms": round(res["graph"] * 1e3, 3),
+        "eager_Gbps": round(bits / res["eager"] / 1e9, 4), "graph_Gbps": round(bits / res["graph"] / 1e9, 4),
+        "bp_fail_rate": float(st[2]) / B, "fer": fe / B, "variants": tuned["variants"], "scl_lds_budget": tuned["budget"],
+    }
 
 
 def cpu_baseline(info, z, sigma2, frozen, N, K, C, L, T, W64, target_s):

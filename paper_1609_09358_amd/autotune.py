@@ -1,0 +1,110 @@
+"""Autotuner for the BP kernel layout.
+
+For a block length N the library offers several register layouts
+(`polar_bp_variants`): a variant r keeps 2^r nodes of every stage row per
+thread, which fixes the threads per frame (N / 2^r), the frames per workgroup
+(64 * 2^r / N when that exceeds 1), the window structure and hence the LDS
+transpose buffers.  The tuner times each variant on a sample of the caller's
+own frames with the caller's decoding parameters (events on the current
+stream) and keeps the fastest; results are cached per process and optionally
+in a JSON file.
+"""
+import json
+import os
+
+import torch
+
+from . import binding as PB
+
+_CACHE = {}
+
+
+def _key(code, max_iter, stop, weighted):
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{dev}|N={code.N}|K={code.K}|c={code.crc_bits}|it={max_iter}|stop={stop}|w={int(weighted)}"
+
+
+def tune_bp(code: PB.PolarCode, llr: torch.Tensor, max_iter: int, stop: int = 1, weights=None, reps: int = 3,
+            sample: int = 16384, cache_file: str = "") -> dict:
+    """Return {"variant": best, "ms": {variant: ms per call on the sample}}."""
+    key = _key(code, max_iter, stop, weights is not None)
+    if key in _CACHE:
+        return _CACHE[key]
+    if cache_file and os.path.exists(cache_file):
+        with open(cache_file) as fh:
+            disk = json.load(fh)
+        if key in disk:
+            _CACHE[key] = disk[key]
+            return disk[key]
+    sub = llr[: min(sample, llr.shape[0])].contiguous()
+    B = sub.shape[0]
+    out = dict(u_hat=torch.empty((B, code.N), dtype=torch.uint8, device=sub.device),
+               iters=torch.empty(B, dtype=torch.int32, device=sub.device),
+               ok=torch.empty(B, dtype=torch.uint8, device=sub.device))
+    stream = torch.cuda.current_stream()
+    timings = {}
+    for v in PB.polar_bp_variants(code.N):
+        PB.bp_decode_batch(code, sub, max_iter=max_iter, stop=stop, weights=weights, variant=v, out=out)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            PB.bp_decode_batch(code, sub, max_iter=max_iter, stop=stop, weights=weights, variant=v, out=out)
+        e1.record(stream)
+        e1.synchronize()
+        timings[v] = e0.elapsed_time(e1) / reps
+    best = min(timings, key=timings.get)
+    res = {"variant": int(best), "ms": {int(k): round(v, 4) for k, v in timings.items()}}
+    _CACHE[key] = res
+    if cache_file:
+        disk = {}
+        if os.path.exists(cache_file):
+            with open(cache_file) as fh:
+                disk = json.load(fh)
+        disk[key] = res
+        with open(cache_file, "w") as fh:
+            json.dump(disk, fh, indent=1)
+    return res
+
+
+def tune_scl_budget(code: PB.PolarCode, llr: torch.Tensor, L: int, budgets=(0, 8192, 12288, 20480, 40960),
+                    reps: int = 2) -> dict:
+    """Time the list decoder on the frames `llr` for each LDS budget
+    (polar_set_scl_lds_budget; 0 = automatic) and leave the fastest set.
+    Returns {"budget": best, "ms": {budget: ms per call}}."""
+    stream = torch.cuda.current_stream()
+    timings = {}
+    for b in budgets:
+        PB.polar_set_scl_lds_budget(b)
+        out = PB.scl_decode_batch(code, llr, L)
+        ws_bytes = PB.polar_workspace_size(code, llr.shape[0], L)
+        ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=llr.device)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            PB.scl_decode_batch(code, llr, L, out=out, workspace=ws)
+        e1.record(stream)
+        e1.synchronize()
+        timings[b] = e0.elapsed_time(e1) / reps
+    best = min(timings, key=timings.get)
+    PB.polar_set_scl_lds_budget(best)
+    return {"budget": int(best), "ms": {int(k): round(v, 4) for k, v in timings.items()}}
+
+
+def tune_mixed(codes, llr_per_code, max_iter: int, L: int, scl_frames: int = 2048) -> dict:
+    """Per-code BP layout for a mixed plan (each code timed on its own frames,
+    `llr_per_code[c]` of shape [B_c][N_c]) and the list decoder's LDS budget
+    (timed on the frames of the longest code).  Returns {"variants": [...],
+    "budget": ..., "detail": ...}; the budget is left set, so create the plan
+    afterwards."""
+    variants, detail = [], {}
+    for c, (code, llr) in enumerate(zip(codes, llr_per_code)):
+        r = tune_bp(code, llr, max_iter=max_iter, stop=1)
+        variants.append(r["variant"])
+        detail[f"bp_code{c}_N{code.N}_K{code.K}"] = r
+    c_big = max(range(len(codes)), key=lambda c: codes[c].N)
+    sub = llr_per_code[c_big][:scl_frames].contiguous()
+    b = tune_scl_budget(codes[c_big], sub, L)
+    detail["scl"] = b
+    return {"variants": variants, "budget": b["budget"], "detail": detail}

@@ -128,3 +128,26 @@ def test_mixed_edge_cases():
     with pytest.raises(PB.PolarError):
         plan(torch.zeros(256, device="cuda"), big, big64, big64, torch.zeros(65 * 128, dtype=torch.uint8,
                                                                               device="cuda"))
+
+
+def test_autotuned_plan_decodes_identically():
+    """The tuner picks layouts and an LDS budget; decoding results do not
+    depend on them."""
+    from paper_1609_09358_amd import autotune
+    from paper_1609_09358_amd import mixed_workload as MW
+    codes = MW.make_codes(Ns=(256, 1024), rates=(0.5,))
+    batch = MW.ragged_batch(codes, 400, seed=21)
+    base = PB.MixedPlan(codes, max_frames=400, max_iter=50, L=8)
+    out0 = torch.empty(batch["total_info_bits"], dtype=torch.uint8, device="cuda")
+    args = (batch["llr"], batch["code_of_frame"], batch["llr_off"], batch["out_off"])
+    base(*args, out0)
+    try:
+        tuned = autotune.tune_mixed(codes, [rows for _, rows in batch["per_code"]], 50, 8)
+        assert all(v in PB.polar_bp_variants(c.N) for v, c in zip(tuned["variants"], codes))
+        plan = PB.MixedPlan(codes, max_frames=400, max_iter=50, L=8, variants=tuned["variants"])
+        out1 = torch.empty_like(out0)
+        plan(*args, out1, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out0, out1)
+    finally:
+        PB.polar_set_scl_lds_budget(0)
