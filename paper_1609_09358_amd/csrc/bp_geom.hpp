@@ -7,9 +7,13 @@
 // the remaining index bits come from the thread number in increasing order.
 // Across a window boundary one row is re-laid out through LDS.  Its LDS word
 // address is sum_b bit_b(i) * c_b over the index bits (and frame-slot bits),
-// with coefficients that are super-increasing (so the map is injective) and
-// whose residues mod 32 make the lanes of each half-wavefront hit distinct
-// banks in both layouts.
+// with coefficients whose residues mod 32 make the lanes of each
+// half-wavefront hit distinct banks in both layouts and that keep the map
+// injective.  Boundaries inside a wavefront take them greedily (each bit the
+// smallest coefficient with its residue that keeps the map injective, the
+// destination layout's lane bits first), which packs a wavefront's 64 V values
+// into little more than 64 V words; boundaries across wavefronts use
+// super-increasing coefficients.
 #pragma once
 
 namespace polarhip {
@@ -18,6 +22,43 @@ namespace bp {
 constexpr int kBankBits = 5;
 constexpr int kMaxPB = 24;  // pseudo-bits: index bits + frame-slot bits
 constexpr int kMaxBnd = 12;
+
+constexpr int kGreedySpan = 4096;  // words of one wavefront's region, at most
+
+// Greedy injective coefficients: bits order[0..no) in turn get the smallest
+// c >= 1 with c = resid (mod 32) when resid >= 0 (any c otherwise) such that
+// no two bit patterns map to the same word.  Returns the span (words), or a
+// value above kGreedySpan when none fits.
+constexpr int greedy_coefficients(const int* order, int no, const int* resid, int* coef) {
+    bool mem[kGreedySpan] = {};
+    int list[1 << 10] = {};
+    int nl = 1, maxa = 0;
+    mem[0] = true;
+    for (int j = 0; j < no; ++j) {
+        const int pb = order[j];
+        const int step = resid[pb] >= 0 ? 32 : 1;
+        int c = resid[pb] >= 0 ? resid[pb] % 32 : 1;
+        if (c == 0) c = step;
+        for (; c < kGreedySpan; c += step) {
+            bool fits = true;
+            for (int a = 0; a < nl && fits; ++a) {
+                const int x = list[a] + c;
+                fits = x < kGreedySpan && !mem[x];
+            }
+            if (fits) break;
+        }
+        if (c >= kGreedySpan || 2 * nl > (1 << 10)) return kGreedySpan + 1;
+        coef[pb] = c;
+        for (int a = 0; a < nl; ++a) {
+            const int x = list[a] + c;
+            mem[x] = true;
+            list[nl + a] = x;
+            if (x > maxa) maxa = x;
+        }
+        nl *= 2;
+    }
+    return maxa + 1;
+}
 
 constexpr int ilog2c(int v) {
     int r = 0;
@@ -123,15 +164,32 @@ struct Geom {
             for (int pb = 0; pb < NPB; ++pb)
                 if (resid[pb] < 0 && !is_wave_bit(k, pb)) order[no++] = pb;
             int S = 0;
-            for (int j = 0; j < no; ++j) {
-                int pb = order[j];
-                int c = S + 1;
-                if (resid[pb] >= 0) {
-                    int m = 1 << kBankBits;
-                    while (c % m != resid[pb] % m) ++c;
+            if (!B.cross) {
+                // destination layout's lane bits first, then the rest
+                int og[kMaxPB], ng = 0;
+                bool used[kMaxPB] = {};
+                for (int j = 0; j < no; ++j) {
+                    bool lane_b = false;
+                    for (int q = 0; q < 6; ++q) lane_b = lane_b || (tpb(k + 1, q) == order[j]);
+                    if (lane_b) {
+                        og[ng++] = order[j];
+                        used[order[j]] = true;
+                    }
                 }
-                B.c[pb] = c;
-                S += c;
+                for (int j = 0; j < no; ++j)
+                    if (!used[order[j]]) og[ng++] = order[j];
+                S = greedy_coefficients(og, ng, resid, B.c) - 1;
+            } else {
+                for (int j = 0; j < no; ++j) {
+                    int pb = order[j];
+                    int c = S + 1;
+                    if (resid[pb] >= 0) {
+                        int m = 1 << kBankBits;
+                        while (c % m != resid[pb] % m) ++c;
+                    }
+                    B.c[pb] = c;
+                    S += c;
+                }
             }
             B.size = S + 1;
             if (!B.cross && S + 1 > ws) ws = S + 1;
@@ -174,6 +232,7 @@ struct Geom {
         return t;
     }
     static constexpr Table TAB = make_table();
+    static_assert(TAB.words > 0, "layout table");
 
     // register part of the LDS word address of value v in window k at boundary j
     static constexpr int reg_off(int j, int k, int v) {
