@@ -289,6 +289,7 @@ def main():
         extra["copy_calibration_bytes"] = src.numel() * 4
 
     extra["c3_mixed"] = c3_mixed(args.steps)
+    extra["c2_rules"] = c2_rules(args.frames, max(3, args.steps // 4))
 
     cpu = None
     if not args.no_cpu:
@@ -320,6 +321,38 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line))
+
+
+def c2_rules(B, steps, ebn0=2.5):
+    """Plain hybrid N=1024 K=512 CRC-16, i_max=200, L=8 at 2.5 dB with the
+    min-sum rule and with the paper's exact rule, on the same frames."""
+    import torch
+
+    from paper_1609_09358_amd import binding as PB
+    from paper_1609_09358_amd import train_wbp as TW
+
+    code = PB.PolarCode(1024, 512, 16, 0, 2.5)
+    info, _, llr = TW.Trainer(code, 1, 16, seed=1016).frames(B, ebn0=ebn0)
+    res = {}
+    for rule in (0, 1):
+        dec = PB.HybridDecoder(code, max_iter=200, L=8, rule=rule)
+        out = dec(llr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dec(llr, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        out = dec(llr, stats=st)
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        res["exact" if rule else "min_sum"] = {
+            "Gbps": round(B * 512 / dt / 1e9, 4), "ms": round(dt * 1e3, 3), "bp_fail_rate": float(s[2]) / B,
+            "mean_bp_iterations": float(s[3]) / B,
+            "fer": float((out["info"] != info).any(dim=1).float().mean()),
+        }
+    return res
 
 
 def c3_mixed(steps, B=4096, max_iter=200, L=8):

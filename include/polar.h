@@ -118,8 +118,11 @@ polar_status polar_channel_awgn(const uint8_t* x, const float* z, const float* s
  * sweep of L messages over stages n..1; inside a stage all N/2 processing
  * elements update at once.  Initialisation L_{i,n+1} = LLR_i,
  * R_{i,1} = llr_max * f_i; outputs LLR(u_i) = L_{i,1} + R_{i,1}.  The rule is
- * min-sum, g(a,b) = sign(a) sign(b) min(|a|,|b|); channel LLRs and every
- * computed message are clipped to +-llr_max.
+ * min-sum, g(a,b) = sign(a) sign(b) min(|a|,|b|) (rule 0), or the exact
+ * ln((1 + e^(a+b)) / (e^a + e^b)) of Sec. II-B (rule 1, single precision,
+ * evaluated as sign(a) sign(b) min(|a|,|b|) + ln(1 + e^-|a+b|) -
+ * ln(1 + e^-|a-b|)); channel LLRs and every computed message are clipped to
+ * +-llr_max.
  * Early stop after each iteration (Sec. II-B): stop = 1 when the re-encoded
  * estimate u_hat G equals the hard decision on LLR(x), stop = 2 when the CRC
  * of u_hat holds, stop = 0 never.
@@ -135,7 +138,8 @@ typedef struct {
     int32_t max_iter;      /* i_max >= 1 (Sec. III)                               */
     int32_t stop;          /* 0 none, 1 re-encoding check, 2 CRC                  */
     float llr_max;         /* clipping level > 0 (20 in Sec. II-B)                */
-    int32_t rule;          /* 0 min-sum (the only rule this build runs on GPU)    */
+    int32_t rule;          /* 0 min-sum, 1 exact (not with weights, not in mixed
+                              plans)                                              */
     const float* weights;  /* dev [weight_iters][2][n][N] or NULL                 */
     int32_t weight_iters;  /* >= max_iter when weights != NULL                    */
     int32_t variant;       /* kernel layout: 0 automatic, else a value returned by

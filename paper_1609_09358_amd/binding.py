@@ -188,7 +188,7 @@ def polar_channel_awgn(x: torch.Tensor, z: torch.Tensor, sigma2: torch.Tensor) -
 
 
 def bp_decode_batch(code: PolarCode, llr: torch.Tensor, max_iter=100, stop=1, llr_max=20.0, weights=None,
-                    variant=0, soft=False, out=None):
+                    variant=0, soft=False, out=None, rule=0):
     B = llr.shape[0]
     _dev(llr, torch.float32, (B, code.N), "llr")
     if weights is not None:
@@ -200,7 +200,7 @@ def bp_decode_batch(code: PolarCode, llr: torch.Tensor, max_iter=100, stop=1, ll
                    ok=torch.empty(B, dtype=torch.uint8, device=dev))
         if soft:
             out["llr_u"] = torch.empty((B, code.N), dtype=torch.float32, device=dev)
-    p = make_bp_params(max_iter, stop, llr_max, weights, variant)
+    p = make_bp_params(max_iter, stop, llr_max, weights, variant, rule)
     _check(lib().bp_decode_batch(code.handle, _ptr(llr), B, C.byref(p), _ptr(out["u_hat"]), _ptr(out.get("llr_u")),
                                  _ptr(out["iters"]), _ptr(out["ok"]), _stream()))
     return out
@@ -252,10 +252,10 @@ def scl_decode_batch(code: PolarCode, llr: torch.Tensor, L, frame_ids=None, out=
 class HybridDecoder:
     """hybrid_decode_batch with its workspace kept between calls."""
 
-    def __init__(self, code: PolarCode, max_iter=200, L=8, stop=1, llr_max=20.0, weights=None, variant=0):
+    def __init__(self, code: PolarCode, max_iter=200, L=8, stop=1, llr_max=20.0, weights=None, variant=0, rule=0):
         self.code, self.L = code, L
         self.weights = weights
-        self.params = make_bp_params(max_iter, stop, llr_max, weights, variant)
+        self.params = make_bp_params(max_iter, stop, llr_max, weights, variant, rule)
         self.workspace = None
 
     def __call__(self, llr: torch.Tensor, out=None, stats=None):

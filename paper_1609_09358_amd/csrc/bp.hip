@@ -115,7 +115,7 @@ struct FrameIO {
 
 // Decode one frame: thread t of the frame's T threads, frame slot `slot` of
 // its wavefront (T < 64) or workgroup.  Returns the verdict (for queues).
-template <class G, bool WEIGHTED, bool SAVE>
+template <class G, bool WEIGHTED, bool SAVE, int RULE = 0>
 __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io, int max_iter, int stop, float lmax,
                                          const float* __restrict__ W, BpShared<G>& sh, int t, int slot) {
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
@@ -182,8 +182,8 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float r1 = (s == 0) ? prior[v] : Rm[s][v];
                     const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
                     const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
-                    const float gi = g_ms(r1, l2 + r2);
-                    const float gj = g_ms(r1, l1);
+                    const float gi = g_rule<RULE>(r1, l2 + r2);
+                    const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
                         const float* w = Wit + (size_t)(0 * n + s) * N + ib;
                         const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
@@ -195,7 +195,8 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                             sv[v2 << G::wbase(k)] = Rm[s + 1][v2];
                         }
                     } else {
-                        Rm[s + 1][v] = gi;  // |g| <= |r1| <= lmax: the clip is exact
+                        // min-sum: |g| <= |r1| <= lmax, so the clip is exact
+                        Rm[s + 1][v] = RULE == 0 ? gi : clipf(gi, lmax);
                         Rm[s + 1][v2] = clipf(gj + r2, lmax);
                     }
                 }
@@ -223,8 +224,8 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float r1 = (s == 0) ? prior[v] : Rm[s][v];
                     const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
                     const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
-                    const float gi = g_ms(l1, l2 + r2);
-                    const float gj = g_ms(r1, l1);
+                    const float gi = g_rule<RULE>(l1, l2 + r2);
+                    const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
                         const float* w = Wit + (size_t)(1 * n + s) * N + ib;
                         const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
@@ -236,7 +237,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                             sv[v2 << G::wbase(k)] = Lm[s][v2];
                         }
                     } else {
-                        Lm[s][v] = gi;  // |g| <= |l1| <= lmax
+                        Lm[s][v] = RULE == 0 ? gi : clipf(gi, lmax);  // min-sum: |g| <= |l1| <= lmax
                         Lm[s][v2] = clipf(gj + l2, lmax);
                     }
                 }
@@ -311,7 +312,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     return okv;
 }
 
-template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE>
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
     const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
@@ -331,7 +332,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     io.iters = iters_out ? iters_out + frame : nullptr;
     io.ok = ok_out ? ok_out + frame : nullptr;
     io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
-    bp_frame<G, WEIGHTED, SAVE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+    bp_frame<G, WEIGHTED, SAVE, RULE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
 }
 
 // Persistent form for ragged batches: workgroups walk the list ids[0..*count)
@@ -379,7 +380,7 @@ using GatherFn = void (*)(CodeDev, const MixedIo*, const int32_t*, const int32_t
                           uint8_t*, int64_t, int32_t*, uint8_t*, int32_t*, int32_t*);
 
 struct Entry {
-    KernelFn plain, weighted, weighted_save;
+    KernelFn plain, weighted, weighted_save, exact;
     GatherFn gather_plain, gather_weighted;
     int wg, fpw;
 };
@@ -387,7 +388,7 @@ struct Entry {
 template <int NL, int RL>
 constexpr Entry make_entry() {
     return Entry{&bp_kernel<NL, RL, false, false>, &bp_kernel<NL, RL, true, false>, &bp_kernel<NL, RL, true, true>,
-                 &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
+                 &bp_kernel<NL, RL, false, false, 1>, &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
                  Geom<NL, RL>::FPW};
 }
 
@@ -438,7 +439,7 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
     if (B == 0) return POLAR_OK;
     const int64_t blocks = (B + e->fpw - 1) / e->fpw;
     if (blocks > (int64_t)INT32_MAX) return set_error(POLAR_ERR_INVALID_ARG, "bp: batch too large");
-    bp::KernelFn fn = p->weights ? e->weighted : e->plain;
+    bp::KernelFn fn = p->rule == 1 ? e->exact : (p->weights ? e->weighted : e->plain);
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
                        p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
     return hip_check(hipGetLastError(), "bp_kernel launch");
@@ -508,7 +509,9 @@ extern "C" polar_status bp_decode_batch(const polar_code* code, const float* llr
     if (p->stop == 2 && code->c == 0)
         return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: CRC stop needs a code with a CRC");
     if (!(p->llr_max > 0.0f)) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: llr_max must be > 0");
-    if (p->rule != 0) return set_error(POLAR_ERR_UNSUPPORTED, "bp_decode_batch: only the min-sum rule runs on GPU");
+    if (p->rule != 0 && p->rule != 1) return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: rule must be 0 or 1");
+    if (p->rule == 1 && p->weights)
+        return set_error(POLAR_ERR_UNSUPPORTED, "bp_decode_batch: the exact rule has no weighted form");
     if (p->weights && p->weight_iters < p->max_iter)
         return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: weight_iters < max_iter");
     if (p->variant != 0 && !bp_variant_supported(code->n, p->variant))

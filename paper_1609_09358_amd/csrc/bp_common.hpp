@@ -35,6 +35,20 @@ __device__ __forceinline__ float g_ms(float a, float b) {
 
 __device__ __forceinline__ float clipf(float v, float m) { return fminf(fmaxf(v, -m), m); }
 
+// The exact check-node rule of Sec. II-B, ln((1 + e^(a+b)) / (e^a + e^b)),
+// through the identity sgn(a) sgn(b) min(|a|,|b|) + ln(1 + e^-|a+b|) -
+// ln(1 + e^-|a-b|), which never overflows.
+__device__ __forceinline__ float g_exact(float a, float b) {
+    const float m = g_ms(a, b);
+    return (m + log1pf(expf(-fabsf(a + b)))) - log1pf(expf(-fabsf(a - b)));
+}
+
+template <int RULE>
+__device__ __forceinline__ float g_rule(float a, float b) {
+    if constexpr (RULE == 0) return g_ms(a, b);
+    else return g_exact(a, b);
+}
+
 // index bits of thread t in window k, register bits zero
 template <class G, int K>
 __device__ __forceinline__ int idx_base(int t) {

@@ -179,7 +179,8 @@ static polar_status check_bp_params(const polar_code* code, const bp_params* p) 
     if (p->stop < 0 || p->stop > 2) return set_error(POLAR_ERR_INVALID_ARG, "stop must be 0, 1 or 2");
     if (p->stop == 2 && code->c == 0) return set_error(POLAR_ERR_INVALID_ARG, "CRC stop needs a code with a CRC");
     if (!(p->llr_max > 0.0f)) return set_error(POLAR_ERR_INVALID_ARG, "llr_max must be > 0");
-    if (p->rule != 0) return set_error(POLAR_ERR_UNSUPPORTED, "only the min-sum rule runs on GPU");
+    if (p->rule != 0 && p->rule != 1) return set_error(POLAR_ERR_INVALID_ARG, "rule must be 0 or 1");
+    if (p->rule == 1 && p->weights) return set_error(POLAR_ERR_UNSUPPORTED, "the exact rule has no weighted form");
     if (p->weights && p->weight_iters < p->max_iter) return set_error(POLAR_ERR_INVALID_ARG, "weight_iters < max_iter");
     if (p->variant != 0 && !bp_variant_supported(code->n, p->variant))
         return set_error(POLAR_ERR_INVALID_ARG, "unknown BP variant");

@@ -109,6 +109,41 @@ def test_bp_soft_output_vs_f64_oracle(N, K, c, iters):
     assert err.max() <= 1e-4, err.max()
 
 
+@pytest.mark.parametrize("N,K,c", [(128, 64, 0), (1024, 512, 16)])
+@pytest.mark.parametrize("iters", [1, 2, 3])
+def test_bp_exact_rule_soft_output_vs_f64_oracle(N, K, c, iters):
+    """The exact rule of Sec. II-B in single precision against the oracle's
+    double evaluation of the same formula: within 1e-4 for the first three
+    iterations, as for min-sum."""
+    B = 16
+    code, info, u, x, llr = frames(N, K, c, 2.0, 2.0, B, seed=40 + iters)
+    out = PB.bp_decode_batch(code, dev(llr), max_iter=iters, stop=0, soft=True, rule=1)
+    got = host(out["llr_u"]).astype(np.float64)
+    ref = O.bp_batch(llr, code.frozen, c, POLY[c], max_iter=iters, stop=0, rule=1, prec="f64", soft=True)["llr_u"]
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-4, err.max()
+
+
+def test_bp_exact_rule_full_runs_vs_f64_oracle():
+    """Whole decodes (re-encoding stop, up to 40 iterations): the device's
+    single-precision transcendentals differ from the host's double ones in the
+    last bits, so a frame may stop an iteration earlier or later; verdicts and
+    decisions agree on almost every frame, and whenever both stop with ok the
+    decisions are identical."""
+    N, K, c, B = 256, 128, 8, 300
+    code, info, u, x, llr = frames(N, K, c, 2.0, 2.0, B, seed=77)
+    out = PB.bp_decode_batch(code, dev(llr), max_iter=40, stop=1, rule=1)
+    ref = O.bp_batch(llr, code.frozen, c, POLY[c], max_iter=40, stop=1, rule=1, prec="f64")
+    ok, ok_r = host(out["ok"]).astype(bool), ref["ok"].astype(bool)
+    uh = host(out["u_hat"])
+    assert np.mean(ok == ok_r) >= 0.97
+    both = ok & ok_r
+    assert both.sum() > B // 2
+    assert np.array_equal(uh[both], ref["u_hat"][both])
+    it, it_r = host(out["iters"]), ref["iters"]
+    assert np.mean(np.abs(it.astype(int) - it_r) <= 1) >= 0.97
+
+
 @pytest.mark.parametrize("iters", [8, 30])
 def test_bp_long_runs_bit_exact(iters):
     N, K, c = 1024, 512, 16
