@@ -290,6 +290,7 @@ def main():
 
     extra["c3_mixed"] = c3_mixed(args.steps)
     extra["c2_rules"] = c2_rules(args.frames, max(3, args.steps // 4))
+    extra["paper_operating_point"] = paper_operating_point()
 
     cpu = None
     if not args.no_cpu:
@@ -353,6 +354,40 @@ def c2_rules(B, steps, ebn0=2.5):
             "fer": float((out["info"] != info).any(dim=1).float().mean()),
         }
     return res
+
+
+def paper_operating_point(B=16384, reps=3):
+    """The paper's own hybrid configuration (Sec. III): N=4096, R=1/2, BP with
+    the exact rule and i_max=50, CA-SCL L=32 (CRC-16 here), over an Eb/N0
+    sweep; the paper reports at most 34 Mbit/s for it on its GPU."""
+    import torch
+
+    from paper_1609_09358_amd import binding as PB
+    from paper_1609_09358_amd import train_wbp as TW
+
+    code = PB.PolarCode(4096, 2048, 16, 0, 2.5)
+    dec = PB.HybridDecoder(code, max_iter=50, L=32, rule=1)
+    gen = TW.Trainer(code, 1, 16, seed=4096)
+    rows = []
+    for e in (1.5, 2.0, 2.5, 3.0, 3.5):
+        info, _, llr = gen.frames(B, ebn0=e)
+        out = dec(llr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dec(llr, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        out = dec(llr, stats=st)
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        rows.append({"ebn0_db": e, "Gbps": round(B * 2048 / dt / 1e9, 4), "bp_fail_rate": float(s[2]) / B,
+                     "mean_bp_iterations": round(float(s[3]) / B, 3),
+                     "fer": float((out["info"] != info).any(dim=1).float().mean())})
+    best = max(r["Gbps"] for r in rows)
+    return {"frames": B, "points": rows, "max_Gbps": best, "paper_max_Mbps": 34.0,
+            "ratio_to_paper_max": round(best * 1e3 / 34.0, 1)}
 
 
 def c3_mixed(steps, B=4096, max_iter=200, L=8):
