@@ -44,11 +44,11 @@ def _lib(prec: str = "f64"):
                                      _i32p, _u8p]
         lib.orc_sc_frame.argtypes = [_f32p, C.c_int, _u8p, C.c_int, _u8p]
         lib.orc_scl_frame.restype = C.c_int
-        lib.orc_scl_frame.argtypes = [_f32p, C.c_int, _u8p, C.c_int, C.c_uint32, C.c_int, C.c_int,
-                                      _u8p, _u8p, _f64p, _u8p, _f64p]
-        lib.orc_scl_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, C.c_int, C.c_uint32,
+        lib.orc_scl_frame.argtypes = [_f32p, C.c_int, _u8p, _u8p, C.c_int, C.c_uint32, C.c_int,
+                                      C.c_int, _u8p, _u8p, _f64p, _u8p, _f64p]
+        lib.orc_scl_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int, C.c_uint32,
                                       C.c_int, C.c_int, _u8p, _u8p, _f64p]
-        lib.orc_hybrid_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, C.c_int, C.c_int,
+        lib.orc_hybrid_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int, C.c_int,
                                          C.c_uint32, C.c_int, C.c_double, _f64p, C.c_int, _u8p,
                                          _u8p, _i32p]
         lib.orc_wbp_grad_frame.restype = C.c_double
@@ -108,6 +108,21 @@ def crc(bits, c: int, poly: int) -> np.ndarray:
     out = np.zeros(c, np.uint8)
     _lib().orc_crc(_p(b, _u8p), len(b), c, poly, _p(out, _u8p))
     return out
+
+
+def decision_aided_mask(N: int, frozen, n_da: int, design_ebn0_db: float, rate: float) -> np.ndarray:
+    """The n_da most reliable non-frozen positions by Gaussian-approximation
+    mean at the design point (equal means: the higher index counts as more
+    reliable), as a 0/1 mask: the positions a decision-aided list decoder does
+    not branch on (Sec. II-A)."""
+    fr = _u8(frozen)
+    m = ga_means(N, sigma2(design_ebn0_db, rate))
+    cand = [i for i in range(N) if not fr[i]]
+    cand.sort(key=lambda i: (m[i], i), reverse=True)
+    mask = np.zeros(N, np.uint8)
+    for i in cand[:n_da]:
+        mask[i] = 1
+    return mask
 
 
 def polar_transform(u) -> np.ndarray:
@@ -215,16 +230,19 @@ def sc_frame(llr, frozen, rule=0, prec="f64") -> np.ndarray:
     return uh
 
 
-def scl_frame(llr, frozen, L, c=0, poly=0, rule=0, prec="f64", all_paths=False):
+def scl_frame(llr, frozen, L, c=0, poly=0, rule=0, prec="f64", all_paths=False, da=None):
+    """CA-SCL of one frame; `da` (mask [N] or None) marks decision-aided
+    positions, where every path takes its hard decision without branching."""
     llr = _f32(llr)
     fr = _u8(frozen)
+    da = None if da is None else _u8(da)
     N = len(fr)
     uh = np.zeros(N, np.uint8)
     ok = np.zeros(1, np.uint8)
     pm = np.zeros(1, np.float64)
     au = np.zeros((L, N), np.uint8) if all_paths else None
     ap = np.zeros(L, np.float64) if all_paths else None
-    ln = _lib(prec).orc_scl_frame(_p(llr, _f32p), N, _p(fr, _u8p), c, poly, L, rule,
+    ln = _lib(prec).orc_scl_frame(_p(llr, _f32p), N, _p(fr, _u8p), _p(da, _u8p), c, poly, L, rule,
                                   _p(uh, _u8p), _p(ok, _u8p), _p(pm, _f64p), _p(au, _u8p),
                                   _p(ap, _f64p))
     out = dict(u_hat=uh, crc_ok=int(ok[0]), pm=float(pm[0]), n_paths=ln)
@@ -234,21 +252,23 @@ def scl_frame(llr, frozen, L, c=0, poly=0, rule=0, prec="f64", all_paths=False):
     return out
 
 
-def scl_batch(llr, frozen, L, c=0, poly=0, rule=0, prec="f64"):
+def scl_batch(llr, frozen, L, c=0, poly=0, rule=0, prec="f64", da=None):
     fr = _u8(frozen)
+    da = None if da is None else _u8(da)
     N = len(fr)
     llr = _f32(llr).reshape(-1, N)
     B = llr.shape[0]
     uh = np.zeros((B, N), np.uint8)
     ok = np.zeros(B, np.uint8)
     pm = np.zeros(B, np.float64)
-    _lib(prec).orc_scl_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), c, poly, L, rule,
+    _lib(prec).orc_scl_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(da, _u8p), c, poly, L, rule,
                              _p(uh, _u8p), _p(ok, _u8p), _p(pm, _f64p))
     return dict(u_hat=uh, crc_ok=ok, pm=pm)
 
 
-def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, prec="f64"):
+def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, prec="f64", da=None):
     fr = _u8(frozen)
+    da = None if da is None else _u8(da)
     N = len(fr)
     n = N.bit_length() - 1
     llr = _f32(llr).reshape(-1, N)
@@ -259,7 +279,7 @@ def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, pre
     if W is not None:
         W = _f64(W)
         assert W.size >= max_iter * 2 * n * N
-    _lib(prec).orc_hybrid_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), K, c, poly, max_iter,
+    _lib(prec).orc_hybrid_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(da, _u8p), K, c, poly, max_iter,
                                 llr_max, _p(W, _f64p), L, _p(info, _u8p), _p(used, _u8p),
                                 _p(it, _i32p))
     return dict(info=info, used_scl=used, iters=it)

@@ -557,8 +557,8 @@ static void path_copy(scl_path* dst, const scl_path* src, int N) {
 /* Returns the number of paths in the final list.  u_hat gets the selected
  * path; all_u / all_pm (optional, L x N and L) get the whole final list in
  * list order. */
-int orc_scl_frame(const float* llr, int N, const uint8_t* frozen, int c, uint32_t poly,
-                  int L, int rule, uint8_t* u_hat, uint8_t* crc_ok, double* pm_out,
+int orc_scl_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* da, int c,
+                  uint32_t poly, int L, int rule, uint8_t* u_hat, uint8_t* crc_ok, double* pm_out,
                   uint8_t* all_u, double* all_pm) {
     int n = ilog2(N);
     real* ch = (real*)malloc(sizeof(real) * N);
@@ -582,6 +582,14 @@ int orc_scl_frame(const float* llr, int N, const uint8_t* frozen, int c, uint32_
             for (int q = 0; q < len; q++) {
                 cur[q].u[i] = 0;
                 cur[q].pm = cur[q].pm + penalty(lam_i[q], 0, rule);
+            }
+        } else if (da && da[i]) {
+            /* decision-aided position (Sec. II-A): every path takes its own hard
+               decision; the list neither branches nor reorders */
+            for (int q = 0; q < len; q++) {
+                int b = lam_i[q] < 0 ? 1 : 0;
+                cur[q].u[i] = (uint8_t)b;
+                cur[q].pm = cur[q].pm + penalty(lam_i[q], b, rule);
             }
         } else {
             int nc = 0;
@@ -636,10 +644,10 @@ int orc_scl_frame(const float* llr, int N, const uint8_t* frozen, int c, uint32_
     return len;
 }
 
-void orc_scl_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, int c, uint32_t poly,
-                   int L, int rule, uint8_t* u_hat, uint8_t* crc_ok, double* pm) {
+void orc_scl_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, const uint8_t* da,
+                   int c, uint32_t poly, int L, int rule, uint8_t* u_hat, uint8_t* crc_ok, double* pm) {
     for (int64_t f = 0; f < B; f++)
-        orc_scl_frame(llr + f * N, N, frozen, c, poly, L, rule, u_hat + f * N, crc_ok + f,
+        orc_scl_frame(llr + f * N, N, frozen, da, c, poly, L, rule, u_hat + f * N, crc_ok + f,
                       pm ? pm + f : NULL, NULL, NULL);
 }
 
@@ -650,9 +658,9 @@ void orc_scl_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, in
 /* bits of whichever result is kept.                                          */
 /* ------------------------------------------------------------------------ */
 
-void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, int K, int c,
-                      uint32_t poly, int max_iter, double llr_max, const double* W, int L,
-                      uint8_t* info_out, uint8_t* used_scl, int32_t* iters) {
+void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, const uint8_t* da,
+                      int K, int c, uint32_t poly, int max_iter, double llr_max, const double* W,
+                      int L, uint8_t* info_out, uint8_t* used_scl, int32_t* iters) {
     uint8_t* u = (uint8_t*)malloc(N);
     for (int64_t f = 0; f < B; f++) {
         uint8_t ok = 0, cok = 0;
@@ -660,7 +668,7 @@ void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
                               NULL, NULL, &ok, NULL);
         if (iters) iters[f] = it;
         used_scl[f] = (uint8_t)(ok ? 0 : 1);
-        if (!ok) orc_scl_frame(llr + f * N, N, frozen, c, poly, L, 0, u, &cok, NULL, NULL, NULL);
+        if (!ok) orc_scl_frame(llr + f * N, N, frozen, da, c, poly, L, 0, u, &cok, NULL, NULL, NULL);
         int q = 0;
         for (int i = 0; i < N && q < K; i++)
             if (!frozen[i]) info_out[f * K + q++] = u[i];

@@ -220,6 +220,67 @@ def test_scl_path_metric_is_codeword_metric(rule):
             assert abs(out["all_pm"][q] - ref) <= 1e-9 * max(1.0, ref)
 
 
+# ------------------------------------------------------------------ decision-aided SCL (Sec. II-A)
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_decision_aided_everywhere_is_sc(rule):
+    """With every non-frozen position decision-aided no path ever branches, so
+    the list decoder is SC whatever L."""
+    N, K = 256, 128
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 1.0, seed=51 + rule, B=5)
+    da = (fr == 0).astype(np.uint8)
+    for prec in ("f64", "f32"):
+        for f in range(5):
+            sc = O.sc_frame(llr[f], fr, rule=rule, prec=prec)
+            for L in (1, 4, 32):
+                got = O.scl_frame(llr[f], fr, L, rule=rule, prec=prec, da=da)
+                assert np.array_equal(got["u_hat"], sc) and got["n_paths"] == 1
+
+
+def test_decision_aided_nowhere_is_plain_scl():
+    N, K, c, poly = 256, 120, 8, 0x07
+    fr, info, u, x, llr = _frame(N, K, c, poly, 1.0, seed=52, B=6)
+    a = O.scl_batch(llr, fr, 8, c, poly)
+    b = O.scl_batch(llr, fr, 8, c, poly, da=np.zeros(N, np.uint8))
+    assert all(np.array_equal(a[k], b[k]) for k in ("u_hat", "crc_ok", "pm"))
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_decision_aided_path_metrics_are_codeword_metrics(rule):
+    """Decision-aided positions take the hard decision, so every surviving
+    path's metric is still its re-encoded codeword's metric, and each of those
+    positions agrees with the hard decision of its path's LLR (the decoded
+    codeword is consistent with the decisions)."""
+    N, K, L, n_da = 256, 128, 8, 40
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 1.0, seed=53 + rule, B=4)
+    da = O.decision_aided_mask(N, fr, n_da, 2.0, K / N)
+    for f in range(4):
+        out = O.scl_frame(llr[f], fr, L, rule=rule, all_paths=True, da=da)
+        l64 = llr[f].astype(np.float64)
+        for q in range(out["n_paths"]):
+            xq = O.polar_transform(out["all_u"][q]).astype(np.int64)
+            if rule == 0:
+                ref = np.sum(np.abs(l64) * (xq != (l64 < 0)))
+            else:
+                ref = np.sum(np.logaddexp(0.0, -(1 - 2 * xq) * l64))
+            assert abs(out["all_pm"][q] - ref) <= 1e-9 * max(1.0, ref)
+
+
+def test_decision_aided_mask_is_most_reliable():
+    N, K, c, design = 1024, 512, 16, 2.5
+    fr = O.ga_frozen(N, K + c, design, K / N)
+    m = O.ga_means(N, O.sigma2(design, K / N))
+    prev = np.zeros(N, np.uint8)
+    for n_da in (0, 1, 50, 300, K + c):
+        da = O.decision_aided_mask(N, fr, n_da, design, K / N)
+        assert da.sum() == n_da and np.all(da <= (fr == 0)) and np.all(prev <= da)
+        if 0 < n_da < K + c:
+            rest = (fr == 0) & (da == 0)
+            assert m[da == 1].min() >= m[rest].max()
+        prev = da
+    assert np.array_equal(prev, (fr == 0).astype(np.uint8))
+
+
 def test_scl_crc_selection_rule():
     N, K, c, poly, L = 128, 56, 8, 0x07, 8
     fr, info, u, x, llr = _frame(N, K, c, poly, 0.5, seed=77, design=2.0, B=40)
