@@ -71,6 +71,11 @@ typedef struct {
     double design_ebn0_db;  /* design point of the construction (frozen == NULL)     */
     const uint8_t* frozen;  /* host [N], 1 = frozen, or NULL; must contain exactly
                                N - K - c ones                                        */
+    int32_t da_bits;        /* decision-aided list decoding (Sec. II-A): the da_bits
+                               most reliable non-frozen positions (Gaussian
+                               approximation at design_ebn0_db, ties: higher index)
+                               are decided by every path's hard decision without
+                               branching; 0 <= da_bits <= K + c, 0 = plain CA-SCL   */
 } polar_code_desc;
 
 /* Builds a code and uploads its tables to the current HIP device.  On success
@@ -95,6 +100,8 @@ polar_status polar_code_params(const polar_code* code, int32_t* N, int32_t* K,
 
 /* Copies the frozen mask (1 = frozen) to host memory [N]. */
 polar_status polar_code_frozen(const polar_code* code, uint8_t* host_mask);
+/* host_mask [N] <- 1 at the decision-aided positions of the list decoder. */
+polar_status polar_code_decision_aided(const polar_code* code, uint8_t* host_mask);
 
 /* ---------------------------------------------------------------------------
  * Encoder (Sec. II, Fig. 1).

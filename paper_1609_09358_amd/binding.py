@@ -27,7 +27,7 @@ class PolarError(RuntimeError):
 
 class polar_code_desc(C.Structure):
     _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("crc_bits", C.c_int32), ("crc_poly", C.c_uint32),
-                ("design_ebn0_db", C.c_double), ("frozen", C.POINTER(C.c_uint8))]
+                ("design_ebn0_db", C.c_double), ("frozen", C.POINTER(C.c_uint8)), ("da_bits", C.c_int32)]
 
 
 class bp_params(C.Structure):
@@ -54,6 +54,7 @@ def lib():
             "polar_construct_frozen": [i32, i32, i32, C.c_double, C.POINTER(C.c_uint8)],
             "polar_code_params": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(u32)],
             "polar_code_frozen": [vp, C.POINTER(C.c_uint8)],
+            "polar_code_decision_aided": [vp, C.POINTER(C.c_uint8)],
             "polar_encode": [vp, vp, i64, vp, vp, vp],
             "polar_channel_awgn": [vp, vp, vp, i64, i32, vp, vp],
             "bp_decode_batch": [vp, vp, i64, C.POINTER(bp_params), vp, vp, vp, vp, vp],
@@ -117,9 +118,10 @@ def _dev(t, dtype, shape, name):
 class PolarCode:
     """Owner of a polar_code handle (frozen set and device tables)."""
 
-    def __init__(self, N, K, crc_bits=0, crc_poly=0, design_ebn0_db=2.0, frozen=None):
+    def __init__(self, N, K, crc_bits=0, crc_poly=0, design_ebn0_db=2.0, frozen=None, da_bits=0):
         d = polar_code_desc()
         d.N, d.K, d.crc_bits = N, K, crc_bits
+        d.da_bits = da_bits
         d.crc_poly = crc_poly
         d.design_ebn0_db = design_ebn0_db
         self._frozen_in = None
@@ -138,6 +140,9 @@ class PolarCode:
         _check(lib().polar_code_frozen(h, mask.ctypes.data_as(C.POINTER(C.c_uint8))))
         self.frozen = mask
         self.info_pos = np.where(mask == 0)[0]
+        da = np.zeros(self.N, np.uint8)
+        _check(lib().polar_code_decision_aided(h, da.ctypes.data_as(C.POINTER(C.c_uint8))))
+        self.decision_aided = da
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -459,6 +464,7 @@ class WeightedBPLoss(torch.autograd.Function):
 
 
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
+            "polar_code_decision_aided",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",

@@ -155,6 +155,7 @@ void polar_free_code(polar_code* code) {
     (void)hipFree(code->d_syn);
     (void)hipFree(code->d_syn_nib);
     (void)hipFree(code->d_enc_crc);
+    (void)hipFree(code->d_da_bits);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete code;
 }
@@ -168,22 +169,27 @@ static polar_status validate_sizes(int N, int K, int c) {
     return POLAR_OK;
 }
 
-static void ga_frozen_mask(int N, int K, int c, double design_ebn0_db, uint8_t* frozen) {
+// positions ordered from the most reliable (Gaussian approximation at the
+// design point, rate K/N); equal means: higher index first
+static std::vector<int> reliability_order(int N, int K, double design_ebn0_db) {
     int n = 0;
     while ((1 << n) < N) ++n;
-    const int k = K + c;
     const double rate = double(K) / double(N);
     const double sigma2 = 1.0 / (2.0 * rate * std::pow(10.0, design_ebn0_db / 10.0));
     std::vector<double> m = ga_bit_channel_means(n, sigma2);
     std::vector<int> order(N);
     std::iota(order.begin(), order.end(), 0);
-    // most reliable first; equal means: higher index first
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         if (m[a] != m[b]) return m[a] > m[b];
         return a > b;
     });
+    return order;
+}
+
+static void ga_frozen_mask(int N, int K, int c, double design_ebn0_db, uint8_t* frozen) {
+    const std::vector<int> order = reliability_order(N, K, design_ebn0_db);
     for (int i = 0; i < N; ++i) frozen[i] = 1;
-    for (int q = 0; q < k; ++q) frozen[order[q]] = 0;
+    for (int q = 0; q < K + c; ++q) frozen[order[q]] = 0;
 }
 
 polar_status polar_construct_frozen(int32_t N, int32_t K, int32_t crc_bits, double design_ebn0_db,
@@ -220,6 +226,18 @@ polar_status polar_build_code(const polar_code_desc* d, polar_code** out) {
     } else {
         ga_frozen_mask(N, K, c, d->design_ebn0_db, frozen.data());
     }
+    if (d->da_bits < 0 || d->da_bits > k)
+        return set_error(POLAR_ERR_INVALID_ARG, "da_bits must be in [0, K + crc_bits]");
+    std::vector<uint8_t> da(N, 0);
+    if (d->da_bits > 0) {
+        const std::vector<int> order = reliability_order(N, K, d->design_ebn0_db);
+        int taken = 0;
+        for (int q = 0; q < N && taken < d->da_bits; ++q)
+            if (!frozen[order[q]]) {
+                da[order[q]] = 1;
+                ++taken;
+            }
+    }
 
     polar_code* code = new polar_code();
     code->N = N;
@@ -229,6 +247,7 @@ polar_status polar_build_code(const polar_code_desc* d, polar_code** out) {
     code->k = k;
     code->poly = poly;
     code->frozen = frozen;
+    code->da = da;
     (void)hipGetDevice(&code->device);
     for (int i = 0; i < N; ++i)
         if (!frozen[i]) code->info_pos.push_back((int16_t)i);
@@ -237,6 +256,9 @@ polar_status polar_build_code(const polar_code_desc* d, polar_code** out) {
     std::vector<uint32_t> fbits(std::max(N / 32, 1), 0u);
     for (int i = 0; i < N; ++i)
         if (frozen[i]) fbits[i / 32] |= 1u << (i % 32);
+    std::vector<uint32_t> dbits(std::max(N / 32, 1), 0u);
+    for (int i = 0; i < N; ++i)
+        if (da[i]) dbits[i / 32] |= 1u << (i % 32);
     std::vector<uint32_t> enc(K, 0u);
     if (c)
         for (int q = 0; q < K; ++q) enc[q] = crc_of_single_one(poly, c, K - 1 - q);
@@ -258,7 +280,8 @@ polar_status polar_build_code(const polar_code_desc* d, polar_code** out) {
         (st = upload(&code->d_info_pos, code->info_pos)) != POLAR_OK ||
         (st = upload(&code->d_syn, syn)) != POLAR_OK ||
         (st = upload(&code->d_syn_nib, nib)) != POLAR_OK ||
-        (st = upload(&code->d_enc_crc, enc)) != POLAR_OK) {
+        (st = upload(&code->d_enc_crc, enc)) != POLAR_OK ||
+        (st = upload(&code->d_da_bits, dbits)) != POLAR_OK) {
         polar_free_code(code);
         return st;
     }
@@ -279,6 +302,12 @@ polar_status polar_code_params(const polar_code* code, int32_t* N, int32_t* K, i
 polar_status polar_code_frozen(const polar_code* code, uint8_t* host_mask) {
     if (!code || !host_mask) return set_error(POLAR_ERR_INVALID_ARG, "polar_code_frozen: null argument");
     std::memcpy(host_mask, code->frozen.data(), code->N);
+    return ok_status();
+}
+
+polar_status polar_code_decision_aided(const polar_code* code, uint8_t* host_mask) {
+    if (!code || !host_mask) return set_error(POLAR_ERR_INVALID_ARG, "polar_code_decision_aided: null argument");
+    std::memcpy(host_mask, code->da.data(), code->N);
     return ok_status();
 }
 

@@ -19,6 +19,7 @@ struct CodeDev {
     const uint32_t* syn;          // [N] CRC syndrome contribution of u_i = 1
     const uint32_t* syn_nib;      // [N/4][16] syndrome of each nibble value
     const uint32_t* enc_crc;      // [K] CRC of the unit vector at info bit q
+    const uint32_t* da_bits;      // [max(N/32,1)] decision-aided positions of the list decoder
     int32_t N, n, K, c, k;
 };
 
@@ -30,12 +31,14 @@ struct polar_code {
     int device;
     std::vector<uint8_t> frozen;    // host [N]
     std::vector<int16_t> info_pos;  // host [k]
+    std::vector<uint8_t> da;        // host [N], decision-aided positions
     // device allocations (owned)
     uint32_t* d_frozen_bits = nullptr;
     int16_t* d_info_pos = nullptr;
     uint32_t* d_syn = nullptr;
     uint32_t* d_syn_nib = nullptr;
     uint32_t* d_enc_crc = nullptr;
+    uint32_t* d_da_bits = nullptr;
     polarhip::CodeDev dev() const {
         polarhip::CodeDev d;
         d.frozen_bits = d_frozen_bits;
@@ -43,6 +46,7 @@ struct polar_code {
         d.syn = d_syn;
         d.syn_nib = d_syn_nib;
         d.enc_crc = d_enc_crc;
+        d.da_bits = d_da_bits;
         d.N = N;
         d.n = n;
         d.K = K;

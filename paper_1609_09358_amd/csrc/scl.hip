@@ -200,7 +200,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
 
         for (int j = 0; j < (N >> BL); ++j) {
             const int i0 = j << BL;
-            const uint32_t fw = (code.frozen_bits[i0 >> 5] >> (i0 & 31)) & (BS == 32 ? 0xFFFFFFFFu : ((1u << BS) - 1u));
+            const uint32_t bmask = BS == 32 ? 0xFFFFFFFFu : ((1u << BS) - 1u);
+            const uint32_t fw = (code.frozen_bits[i0 >> 5] >> (i0 & 31)) & bmask;
+            const uint32_t dw = (code.da_bits[i0 >> 5] >> (i0 & 31)) & bmask;  // decision-aided
             // ---------------- block start: levels top..BL, all lanes together
             if (BL < n) {
                 const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
@@ -319,6 +321,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                 uint32_t bit = 0;
                 if ((fw >> r) & 1u) {
                     if (lane < act) PM = PM + (lam0 < 0.0f ? fabsf(lam0) : 0.0f);
+                } else if ((dw >> r) & 1u) {
+                    // decision-aided position (Sec. II-A): every path keeps its
+                    // hard decision; no branching, no metric change, same slots
+                    if (lane < act) {
+                        bit = lam0 < 0.0f ? 1u : 0u;
+                        SYN ^= bit ? code.syn[i] : 0u;
+                        const uint8_t tv = (uint8_t)(lane | (bit << 7));
+                        if (tbg) tbg[infoq * L + lane] = tv;
+                        else tbk[infoq * L + lane] = tv;
+                    }
+                    ++infoq;
                 } else {
                     const int ncand = 2 * act;
                     const int p = lane >> 1, b = lane & 1;

@@ -323,3 +323,33 @@ def test_pipelined_hybrid_edge_cases():
     arr = (C.c_void_p * 1)(empty.data_ptr())
     assert PB.lib().hybrid_decode_pipelined(code.handle, 1, arr, 0, C.byref(p), 4, arr, None, None, None, 0,
                                             C.c_void_p(s), C.c_void_p(s)) == 1
+
+
+# ------------------------------------------------------------------ decision-aided list decoding (Sec. II-A)
+
+@pytest.mark.parametrize("N,K,c,L,n_da", [(64, 24, 8, 4, 6), (256, 120, 8, 8, 40), (1024, 512, 24, 32, 200),
+                                          (2048, 1024, 16, 8, 500), (1024, 512, 16, 8, 528)])
+def test_decision_aided_scl_bit_exact_vs_f32_oracle(N, K, c, L, n_da):
+    B = 9
+    code0, info, u, x, llr = frames(N, K, c, 2.0, 1.5, B, seed=5 * N + n_da)
+    code = PB.PolarCode(N, K, c, 0, 2.0, da_bits=n_da)
+    assert np.array_equal(code.frozen, code0.frozen)
+    da = O.decision_aided_mask(N, code.frozen, n_da, 2.0, K / N)
+    assert np.array_equal(code.decision_aided, da)
+    ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32", da=da)
+    out = PB.scl_decode_batch(code, dev(llr), L)
+    assert np.array_equal(host(out["crc_ok"]), ref["crc_ok"])
+    assert np.array_equal(host(out["pm"]), ref["pm"].astype(np.float32))
+    assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
+
+
+def test_decision_aided_hybrid_bit_exact_vs_f32_oracle():
+    N, K, c, L, it, n_da = 1024, 512, 16, 32, 30, 150
+    B = 40
+    code0, info, u, x, llr = frames(N, K, c, 2.5, 1.5, B, seed=606)
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=n_da)
+    ref = O.hybrid_batch(llr, code.frozen, K, c, POLY[c], it, L, prec="f32", da=code.decision_aided)
+    out = PB.HybridDecoder(code, max_iter=it, L=L)(dev(llr))
+    assert np.array_equal(host(out["used_scl"]), ref["used_scl"])
+    assert np.array_equal(host(out["info"]), ref["info"])
+    assert 0 < ref["used_scl"].sum() < B
