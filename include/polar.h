@@ -295,14 +295,23 @@ polar_status wbp_forward(const polar_code* code, const float* llr, int64_t B, co
 polar_status wbp_bce(const polar_code* code, const float* llr_u, const uint8_t* u_true, int64_t B, double scale,
                      float* loss, float* dlam, hipStream_t stream);
 
+/* The same loss after every one of the T iterations (a loss per iteration,
+ * summed): LLR(u) after iteration t is read from saved (wbp_forward's saved
+ * rows: L row 0 of iteration t plus the frozen prior).  loss dev [B] or NULL,
+ * dlam dev [B][T][N] = scale * d(loss)/d(LLR(u) after iteration t).  Must run
+ * before wbp_backward, which overwrites `saved`. */
+polar_status wbp_bce_multi(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B, int32_t T,
+                           double scale, float* loss, float* dlam, hipStream_t stream);
+
 /* Reverse-mode gradient of the weighted BP: dW dev [T][2][n][N] = sum over the
- * B frames (in frame order, accumulated in double) of d(loss)/dW given dlam =
- * d(loss)/d(llr_u) dev [B][N]; dllr dev [B][N] or NULL = d(loss)/d(llr).
- * `saved` (from wbp_forward with the same llr, W, T) is used as scratch and is
- * undefined afterwards.  Deterministic. */
+ * B frames (in frame order, accumulated in double) of d(loss)/dW given dlam
+ * dev [B][dlam_iters][N]: d(loss)/d(llr_u) after the last iteration
+ * (dlam_iters = 1) or after every iteration (dlam_iters = T); dllr dev [B][N]
+ * or NULL = d(loss)/d(llr).  `saved` (from wbp_forward with the same llr, W,
+ * T) is used as scratch and is undefined afterwards.  Deterministic. */
 polar_status wbp_backward(const polar_code* code, const float* llr, int64_t B, const float* W, int32_t T,
-                          float llr_max, int32_t variant, float* saved, const float* dlam, float* dW, float* dllr,
-                          hipStream_t stream);
+                          float llr_max, int32_t variant, float* saved, const float* dlam, int32_t dlam_iters,
+                          float* dW, float* dllr, hipStream_t stream);
 
 /* One Adam step (Kingma and Ba, 2015) on `count` float parameters, step >= 1:
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr m_hat / (sqrt(v_hat) + eps)

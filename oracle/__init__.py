@@ -54,9 +54,9 @@ def _lib(prec: str = "f64"):
         lib.orc_wbp_grad_frame.restype = C.c_double
         lib.orc_wbp_grad_batch.restype = C.c_double
         lib.orc_wbp_grad_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int,
-                                           C.c_double, _f64p, C.c_double, _f64p, _f64p]
+                                           C.c_double, _f64p, C.c_double, C.c_int, _f64p, _f64p]
         lib.orc_wbp_backward_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, C.c_int, C.c_double, _f64p,
-                                               _f64p, _f64p, _f64p]
+                                               _f64p, C.c_int, _f64p, _f64p]
         lib.orc_adam_step.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_double]
         _LIBS[prec] = lib
@@ -285,10 +285,12 @@ def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, pre
     return dict(info=info, used_scl=used, iters=it)
 
 
-def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", want_dllr=False):
+def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", want_dllr=False, multi=False):
     """Loss and gradients of the weighted BP (batch).  Returns (loss, dW[, dllr]).
 
-    scale defaults to 1 / (B * k), the mean over frames and non-frozen bits."""
+    The loss is the BCE of LLR(u) after the last iteration, or (multi) the sum
+    of that BCE after every iteration.  scale defaults to 1 / (B * k) (times
+    1 / T for multi): the mean over frames, non-frozen bits (and iterations)."""
     fr = _u8(frozen)
     N = len(fr)
     n = N.bit_length() - 1
@@ -297,12 +299,12 @@ def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", wa
     B = llr.shape[0]
     k = int((fr == 0).sum())
     if scale is None:
-        scale = 1.0 / (B * k)
+        scale = 1.0 / (B * k * (T if multi else 1))
     W = _f64(W).reshape(T, 2, n, N)
     dW = np.zeros((T, 2, n, N), np.float64)
     dl = np.zeros((B, N), np.float64) if want_dllr else None
     loss = _lib(prec).orc_wbp_grad_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(u_true, _u8p),
-                                         T, llr_max, _p(W, _f64p), scale, _p(dW, _f64p),
+                                         T, llr_max, _p(W, _f64p), scale, int(multi), _p(dW, _f64p),
                                          _p(dl, _f64p))
     if want_dllr:
         return loss, dW, dl
@@ -310,7 +312,8 @@ def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", wa
 
 
 def wbp_backward(llr, frozen, T, W, dlam, llr_max=20.0, prec="f64"):
-    """Adjoint of the weighted BP for a given d loss / d lambda ([B][N]).
+    """Adjoint of the weighted BP for a given d loss / d lambda: [B][N] (after
+    the last iteration) or [B][T][N] (after every iteration).
     Returns (dW [T][2][n][N] summed over frames in frame order, dllr [B][N])."""
     fr = _u8(frozen)
     N = len(fr)
@@ -318,11 +321,13 @@ def wbp_backward(llr, frozen, T, W, dlam, llr_max=20.0, prec="f64"):
     llr = _f32(llr).reshape(-1, N)
     B = llr.shape[0]
     W = _f64(W).reshape(T, 2, n, N)
-    dlam = _f64(dlam).reshape(B, N)
+    dlam = _f64(dlam)
+    nl = T if dlam.size == B * T * N and dlam.size != B * N else 1
+    dlam = dlam.reshape(B, nl, N)
     dW = np.zeros((T, 2, n, N), np.float64)
     dl = np.zeros((B, N), np.float64)
     _lib(prec).orc_wbp_backward_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), T, llr_max, _p(W, _f64p),
-                                      _p(dlam, _f64p), _p(dW, _f64p), _p(dl, _f64p))
+                                      _p(dlam, _f64p), nl, _p(dW, _f64p), _p(dl, _f64p))
     return dW, dl
 
 

@@ -699,7 +699,8 @@ static void g_partials(real a, real b, real* da, real* db) {
 /* Adjoint of the weighted BP given dlam = d loss / d lambda (N values; zero on
  * frozen positions): accumulates dW (double) and writes dllr (optional). */
 void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int T, double llr_max,
-                            const double* W, const double* dlam, double* dW, double* dllr) {
+                            const double* W, const double* dlam, int dlam_iters, double* dW,
+                            double* dllr) {
     int n = ilog2(N);
     real lmax = (real)llr_max;
     size_t per = (size_t)2 * n * N;
@@ -718,7 +719,6 @@ void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int 
     /* adjoints of the current message rows */
     real* aL = (real*)calloc((size_t)(n + 1) * N, sizeof(real));
     real* aR = (real*)calloc((size_t)(n + 1) * N, sizeof(real));
-    for (int i = 0; i < N; i++) aL[0 * N + i] = (real)dlam[i];
 #define SAVED_R(t, s, i) ((real)save[(size_t)(t) * per + ((size_t)0 * n + (s)) * N + (i)])
 #define SAVED_L(t, s, i) ((real)save[(size_t)(t) * per + ((size_t)1 * n + (s)) * N + (i)])
     /* value of row r of R during iteration t (0-based): row 0 constant, row r >= 1 saved */
@@ -727,6 +727,13 @@ void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int 
 #define LV(t, r, i) ((r) == n ? Rch[i] : ((t) < 0 ? (real)0 : SAVED_L(t, r, i)))
     for (int t = T - 1; t >= 0; t--) {
         const double* Wt = W ? W + (size_t)t * per : NULL;
+        /* the loss reads LLR(u) after iteration t (every iteration when
+         * dlam_iters == T, the last one when it is 1); row 0 of L feeds
+         * nothing else, so its adjoint is exactly d loss / d lambda_t */
+        if (dlam_iters == T || t == T - 1) {
+            const double* dl = dlam + (size_t)(dlam_iters == T ? t : 0) * N;
+            for (int i = 0; i < N; i++) aL[0 * N + i] = (real)dl[i];
+        }
         /* undo the L sweep: forward order s = n-1..0, reverse s = 0..n-1 */
         for (int s = 0; s < n; s++) {
             int d = 1 << s;
@@ -815,43 +822,54 @@ void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int 
 }
 
 double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* u_true,
-                          int T, double llr_max, const double* W, double scale,
+                          int T, double llr_max, const double* W, double scale, int multi,
                           double* dW /* [T][2][n][N], accumulated */, double* dllr /* N or NULL */) {
+    int n = ilog2(N);
+    size_t per = (size_t)2 * n * N;
     uint8_t* uh = (uint8_t*)malloc(N);
     uint8_t ok;
     double* lam = (double*)malloc(sizeof(double) * N);
-    double* dlam = (double*)calloc(N, sizeof(double));
-    orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, lam, NULL, &ok, NULL);
+    int nl = multi ? T : 1;
+    double* dlam = (double*)calloc((size_t)nl * N, sizeof(double));
+    double* save = multi ? (double*)malloc(sizeof(double) * per * T) : NULL;
+    orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, lam, NULL, &ok, save);
     double loss = 0.0;
-    for (int i = 0; i < N; i++) {
-        if (frozen[i]) continue;
-        double sgn_u = u_true[i] ? 1.0 : -1.0;
-        double z = sgn_u * lam[i];
-        loss += softplus(z);
-        /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
-        double sig = 1.0 / (1.0 + exp(-z));
-        dlam[i] = (double)(real)(scale * sgn_u * sig);
+    for (int q = 0; q < nl; q++) {
+        int t = multi ? q : T - 1;
+        for (int i = 0; i < N; i++) {
+            if (frozen[i]) continue;
+            /* LLR(u_i) after iteration t: L row 0 plus the (zero) prior of a
+             * non-frozen position, added in working precision as in BP */
+            double lt = multi ? (double)((real)save[(size_t)t * per + (size_t)n * N + i] + (real)0) : lam[i];
+            double sgn_u = u_true[i] ? 1.0 : -1.0;
+            double z = sgn_u * lt;
+            loss += softplus(z);
+            /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
+            double sig = 1.0 / (1.0 + exp(-z));
+            dlam[(size_t)q * N + i] = (double)(real)(scale * sgn_u * sig);
+        }
     }
-    orc_wbp_backward_frame(llr, N, frozen, T, llr_max, W, dlam, dW, dllr);
+    orc_wbp_backward_frame(llr, N, frozen, T, llr_max, W, dlam, nl, dW, dllr);
     free(uh);
     free(lam);
     free(dlam);
+    free(save);
     return loss * scale;
 }
 
 void orc_wbp_backward_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, int T, double llr_max,
-                            const double* W, const double* dlam, double* dW, double* dllr) {
+                            const double* W, const double* dlam, int dlam_iters, double* dW, double* dllr) {
     for (int64_t f = 0; f < B; f++)
-        orc_wbp_backward_frame(llr + f * N, N, frozen, T, llr_max, W, dlam + f * N, dW,
-                               dllr ? dllr + f * N : NULL);
+        orc_wbp_backward_frame(llr + f * N, N, frozen, T, llr_max, W, dlam + (size_t)f * dlam_iters * N,
+                               dlam_iters, dW, dllr ? dllr + f * N : NULL);
 }
 
 double orc_wbp_grad_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
                           const uint8_t* u_true, int T, double llr_max, const double* W,
-                          double scale, double* dW, double* dllr) {
+                          double scale, int multi, double* dW, double* dllr) {
     double loss = 0.0;
     for (int64_t f = 0; f < B; f++)
-        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, dW,
+        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, multi, dW,
                                    dllr ? dllr + f * N : NULL);
     return loss;
 }

@@ -64,7 +64,8 @@ def lib():
             "polar_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
             "wbp_forward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp],
             "wbp_bce": [vp, vp, vp, i64, C.c_double, vp, vp, vp],
-            "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp, vp],
+            "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, i32, vp, vp, vp],
+            "wbp_bce_multi": [vp, vp, vp, i64, i32, C.c_double, vp, vp, vp],
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "polar_set_scl_lds_budget": [i64],
             "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
@@ -418,18 +419,36 @@ def wbp_bce(code: PolarCode, llr_u, u_true, scale=None, want_loss=True):
     return loss, dlam
 
 
+def wbp_bce_multi(code: PolarCode, saved, u_true, T, scale=None, want_loss=True):
+    """Per-frame loss summed over all T iterations (times scale) and
+    d loss / d LLR(u) after every iteration, [B][T][N]; scale defaults to
+    1/(B k T).  Call before wbp_backward, which consumes `saved`."""
+    B = saved.shape[0]
+    _dev(saved, torch.float32, (B, T, 2, code.n, code.N), "saved")
+    _dev(u_true, torch.uint8, (B, code.N), "u_true")
+    if scale is None:
+        scale = 1.0 / (B * code.k * T)
+    dlam = torch.empty((B, T, code.N), dtype=torch.float32, device=saved.device)
+    loss = torch.empty(B, dtype=torch.float32, device=saved.device) if want_loss else None
+    _check(lib().wbp_bce_multi(code.handle, _ptr(saved), _ptr(u_true), B, T, float(scale), _ptr(loss), _ptr(dlam),
+                               _stream()))
+    return loss, dlam
+
+
 def wbp_backward(code: PolarCode, llr, W, saved, dlam, llr_max=20.0, variant=0, want_dllr=False):
-    """Weight gradient (summed over frames) and optionally d/d llr; `saved` is consumed."""
+    """Weight gradient (summed over frames) and optionally d/d llr; `saved` is
+    consumed.  dlam: [B][N] (loss after the last iteration) or [B][T][N]."""
     B = llr.shape[0]
     T = W.shape[0]
     _dev(llr, torch.float32, (B, code.N), "llr")
     _dev(W, torch.float32, (T, 2, code.n, code.N), "W")
     _dev(saved, torch.float32, (B, T, 2, code.n, code.N), "saved")
-    _dev(dlam, torch.float32, (B, code.N), "dlam")
+    dlam_iters = T if dlam.dim() == 3 else 1
+    _dev(dlam, torch.float32, (B, T, code.N) if dlam.dim() == 3 else (B, code.N), "dlam")
     dW = torch.empty_like(W)
     dllr = torch.empty_like(llr) if want_dllr else None
     _check(lib().wbp_backward(code.handle, _ptr(llr), B, _ptr(W), T, llr_max, variant, _ptr(saved), _ptr(dlam),
-                              _ptr(dW), _ptr(dllr), _stream()))
+                              dlam_iters, _ptr(dW), _ptr(dllr), _stream()))
     return dW, dllr
 
 
@@ -467,6 +486,6 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "polar_code_decision_aided",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
-            "wbp_backward", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
+            "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_mixed_create", "polar_mixed_decode",
             "polar_mixed_decode_graph", "polar_mixed_free"]

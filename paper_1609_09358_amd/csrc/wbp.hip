@@ -35,7 +35,7 @@ __device__ __forceinline__ void g_partials(float a, float b, float& da, float& d
 template <int NLOG, int RLOG>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void wbp_bwd_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int T, float lmax, const float* __restrict__ W,
-    float* __restrict__ saved, const float* __restrict__ dlam, float* __restrict__ dllr) {
+    float* __restrict__ saved, const float* __restrict__ dlam, int dlam_iters, float* __restrict__ dllr) {
     using G = Geom<NLOG, RLOG>;
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
     __shared__ float tb[G::TAB.words];
@@ -69,7 +69,6 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void wbp_bwd_kernel(
         for (int v = 0; v < V; ++v) {
             const int i = ib + v;
             prior[v] = ((code.frozen_bits[i >> 5] >> (i & 31)) & 1u) ? lmax : 0.0f;
-            aL[0][v] = dlam[frame * N + i];
         }
     }
     {
@@ -83,6 +82,14 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void wbp_bwd_kernel(
     float* S = saved + (size_t)frame * T * 2 * n * N;
 
     for (int it = T - 1; it >= 0; --it) {
+        // the loss reads LLR(u) after this iteration (every iteration, or only
+        // the last); row 0 of L feeds nothing else, so its adjoint is d loss / d lambda
+        if (dlam_iters == T || it == T - 1) {
+            const int ib = idx_base<G, 0>(t);
+            const float* dl = dlam + ((size_t)frame * dlam_iters + (dlam_iters == T ? it : 0)) * N;
+#pragma unroll
+            for (int v = 0; v < V; ++v) aL[0][v] = dl[ib + v];
+        }
         const float* Wit = W + (size_t)it * 2 * n * N;
         float* St = S + (size_t)it * 2 * n * N;
         const float* Sprev = S + (size_t)(it > 0 ? it - 1 : 0) * 2 * n * N;
@@ -199,7 +206,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void wbp_bwd_kernel(
     }
 }
 
-using BwdFn = void (*)(CodeDev, const float*, int64_t, int, float, const float*, float*, const float*, float*);
+using BwdFn = void (*)(CodeDev, const float*, int64_t, int, float, const float*, float*, const float*, int, float*);
 
 struct BwdEntry {
     BwdFn fn;
@@ -276,6 +283,45 @@ __global__ __launch_bounds__(256) void wbp_bce_kernel(CodeDev code, const float*
     }
 }
 
+// per-iteration loss of frame f (one block): LLR(u) after iteration t = saved
+// L row 0 of iteration t + the frozen prior (0 on the non-frozen positions the
+// loss reads); the loss sums over iterations and positions in double
+__global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const float* __restrict__ saved,
+                                                            const uint8_t* __restrict__ u, int T, double scale,
+                                                            float* __restrict__ loss, float* __restrict__ dlam) {
+    __shared__ double red[256 / 64];
+    const int64_t f = blockIdx.x;
+    const int N = code.N, n = code.n;
+    double acc = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const float* lrow = saved + (((size_t)f * T + t) * 2 * n + n) * N;
+        float* drow = dlam + ((size_t)f * T + t) * N;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const bool fr = (code.frozen_bits[i >> 5] >> (i & 31)) & 1u;
+            float d = 0.0f;
+            if (!fr) {
+                const float lam = lrow[i] + 0.0f;
+                const double s = u[f * N + i] ? 1.0 : -1.0;
+                const double z = s * (double)lam;
+                acc += z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));
+                const double sig = 1.0 / (1.0 + exp(-z));
+                d = (float)(scale * s * sig);
+            }
+            drow[i] = d;
+        }
+    }
+    if (loss) {
+        for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < (int)(blockDim.x / 64); ++w) tot += red[w];
+            loss[f] = (float)(tot * scale);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t count,
                                                    float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -318,12 +364,26 @@ extern "C" polar_status wbp_bce(const polar_code* code, const float* llr_u, cons
     return st == POLAR_OK ? ok_status() : st;
 }
 
+extern "C" polar_status wbp_bce_multi(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
+                                      int32_t T, double scale, float* loss, float* dlam, hipStream_t stream) {
+    if (!code || (B > 0 && (!saved || !u_true || !dlam)))
+        return set_error(POLAR_ERR_INVALID_ARG, "wbp_bce_multi: null argument");
+    if (B < 0 || T < 1 || B > (int64_t)INT32_MAX) return set_error(POLAR_ERR_INVALID_ARG, "wbp_bce_multi: bad sizes");
+    if (B == 0) return ok_status();
+    hipLaunchKernelGGL(wbp_bce_multi_kernel, dim3((unsigned)B), dim3(256), 0, stream, code->dev(), saved, u_true, T,
+                       scale, loss, dlam);
+    polar_status st = hip_check(hipGetLastError(), "wbp_bce_multi launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
 extern "C" polar_status wbp_backward(const polar_code* code, const float* llr, int64_t B, const float* W, int32_t T,
-                                     float llr_max, int32_t variant, float* saved, const float* dlam, float* dW,
-                                     float* dllr, hipStream_t stream) {
+                                     float llr_max, int32_t variant, float* saved, const float* dlam,
+                                     int32_t dlam_iters, float* dW, float* dllr, hipStream_t stream) {
     if (!code || !W || !dW || (B > 0 && (!llr || !saved || !dlam)))
         return set_error(POLAR_ERR_INVALID_ARG, "wbp_backward: null argument");
     if (B < 0 || T < 1 || !(llr_max > 0.0f)) return set_error(POLAR_ERR_INVALID_ARG, "wbp_backward: bad sizes");
+    if (dlam_iters != 1 && dlam_iters != T)
+        return set_error(POLAR_ERR_INVALID_ARG, "wbp_backward: dlam_iters must be 1 or T");
     const int v = variant ? variant : bp_default_variant(code->n);
     const bp::BwdEntry* e = bp::lookup_bwd(code->n, v);
     if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "wbp_backward: no kernel variant for this block length");
@@ -331,7 +391,7 @@ extern "C" polar_status wbp_backward(const polar_code* code, const float* llr, i
     if (B > 0) {
         const int64_t blocks = (B + e->fpw - 1) / e->fpw;
         hipLaunchKernelGGL(e->fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, T, llr_max, W,
-                           saved, dlam, dllr);
+                           saved, dlam, dlam_iters, dllr);
         polar_status st = hip_check(hipGetLastError(), "wbp_bwd launch");
         if (st != POLAR_OK) return st;
     }

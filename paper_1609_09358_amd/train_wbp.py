@@ -30,8 +30,9 @@ def sigma2_of(ebn0_db: torch.Tensor, rate: float) -> torch.Tensor:
 
 class Trainer:
     def __init__(self, code: PB.PolarCode, T: int, batch: int, lr: float = 1e-3, ebn0=(1.0, 4.0), seed: int = 1,
-                 llr_max: float = 20.0):
+                 llr_max: float = 20.0, multiloss: bool = False):
         self.code, self.T, self.B, self.lr, self.ebn0, self.llr_max = code, T, batch, lr, ebn0, llr_max
+        self.multiloss = multiloss
         dev = torch.device("cuda")
         shape = (T, 2, code.n, code.N)
         self.W = torch.ones(shape, dtype=torch.float32, device=dev)
@@ -59,7 +60,10 @@ class Trainer:
     def train_step(self):
         _, u, llr = self.frames()
         fw = PB.wbp_forward(self.code, llr, self.W, llr_max=self.llr_max, save=True, out=self.out)
-        loss, dlam = PB.wbp_bce(self.code, fw["llr_u"], u)
+        if self.multiloss:
+            loss, dlam = PB.wbp_bce_multi(self.code, fw["saved"], u, self.T)
+        else:
+            loss, dlam = PB.wbp_bce(self.code, fw["llr_u"], u)
         dW, _ = PB.wbp_backward(self.code, llr, self.W, fw["saved"], dlam, llr_max=self.llr_max)
         self.step += 1
         PB.polar_adam_step(self.W, dW, self.m, self.v, self.step, lr=self.lr)

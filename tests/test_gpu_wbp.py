@@ -140,3 +140,42 @@ def test_autograd_function():
     dW, _ = PB.wbp_backward(code, llr_d, W.detach(), fw["saved"], dlam)
     assert torch.equal(W.grad, dW)
     assert float(loss) > 0
+
+
+@pytest.mark.parametrize("N,K,c,T", [(64, 32, 0, 4), (256, 128, 8, 10), (1024, 512, 24, 3)])
+def test_multi_loss_backward_bit_exact_given_dlam(N, K, c, T):
+    """Loss after every iteration: the adjoint takes one d loss / d LLR(u) per
+    iteration and matches the oracle's float build bit for bit."""
+    n = N.bit_length() - 1
+    B = 11
+    code, u, llr = frames(N, K, c, 1.0, B, seed=3 * N + T)
+    W = rand_w(T, n, N, seed=N + 1)
+    llr_d, W_d = dev(llr), dev(W)
+    fw = PB.wbp_forward(code, llr_d, W_d, save=True)
+    _, dlam = PB.wbp_bce_multi(code, fw["saved"], dev(u), T)
+    assert tuple(dlam.shape) == (B, T, N)
+    dW, dllr = PB.wbp_backward(code, llr_d, W_d, fw["saved"], dlam, want_dllr=True)
+    ref_dW, ref_dllr = O.wbp_backward(llr, code.frozen, T, W.astype(np.float64), host(dlam).astype(np.float64),
+                                      prec="f32")
+    assert np.array_equal(host(dW), ref_dW.astype(np.float32))
+    assert np.array_equal(host(dllr), ref_dllr.astype(np.float32))
+
+
+@pytest.mark.parametrize("T", [3, 10])
+def test_multi_loss_end_to_end_vs_oracle(T):
+    N, K, c, B = 256, 128, 8, 48
+    code, u, llr = frames(N, K, c, 2.0, B, seed=123 + T)
+    W = rand_w(T, 8, N, seed=9, lo=0.8, hi=1.2)
+    llr_d, W_d = dev(llr), dev(W)
+    fw = PB.wbp_forward(code, llr_d, W_d, save=True)
+    loss, dlam = PB.wbp_bce_multi(code, fw["saved"], dev(u), T)
+    dW, _ = PB.wbp_backward(code, llr_d, W_d, fw["saved"], dlam)
+    g = host(dW).astype(np.float64)
+    tot = float(host(loss).astype(np.float64).sum())
+    l32, g32 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), multi=True, prec="f32")
+    assert abs(tot - l32) <= 1e-5 * max(1.0, abs(l32))
+    assert np.max(np.abs(g - g32)) <= 1e-5 * np.abs(g32).max()
+    if T <= 3:
+        l64, g64 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), multi=True)
+        assert abs(tot - l64) <= 1e-5 * max(1.0, abs(l64))
+        assert np.max(np.abs(g - g64)) <= 1e-4 * np.abs(g64).max()

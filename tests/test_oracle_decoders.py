@@ -404,6 +404,54 @@ def test_wbp_loss_value():
     assert abs(loss - bce[:, free].mean()) < 1e-9
 
 
+def test_wbp_multi_loss_is_sum_of_truncated_final_losses():
+    """The first t iterations of a T-iteration decoder are a t-iteration
+    decoder, so the loss after every iteration is the sum of the final-iteration
+    losses of the truncated decoders, and its weight gradient the sum of their
+    gradients (padded with zeros for the later iterations)."""
+    N, K, T = 64, 32, 5
+    n = 6
+    rng = np.random.default_rng(17)
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 1.0, seed=72, B=4)
+    W = rng.uniform(0.6, 1.4, (T, 2, n, N))
+    k = int((fr == 0).sum())
+    s = 1.0 / (4 * k)
+    loss_m, dW_m, dl_m = O.wbp_grad(llr, fr, u, T, W, scale=s, multi=True, want_dllr=True)
+    loss_s, dW_s, dl_s = 0.0, np.zeros_like(W), np.zeros_like(dl_m)
+    for t in range(1, T + 1):
+        lt, gt, dlt = O.wbp_grad(llr, fr, u, t, W[:t], scale=s, want_dllr=True)
+        loss_s += lt
+        dW_s[:t] += gt
+        dl_s += dlt
+    assert abs(loss_m - loss_s) <= 1e-12 * max(1.0, abs(loss_s))
+    assert np.allclose(dW_m, dW_s, rtol=1e-9, atol=1e-15)
+    assert np.allclose(dl_m, dl_s, rtol=1e-9, atol=1e-15)
+    assert np.abs(dW_m[0]).sum() > 0
+
+
+def test_wbp_multi_loss_gradient_matches_finite_differences():
+    N, T = 16, 3
+    n = 4
+    K = 8
+    rng = np.random.default_rng(5)
+    fr = O.ga_frozen(N, K, 0.0, 0.5)
+    info = rng.integers(0, 2, (3, K)).astype(np.uint8)
+    u, x = O.encode_batch(info, K, 0, 0, fr)
+    llr = O.channel_llr(x, rng.standard_normal((3, N)), O.sigma2(0.0, 0.5))
+    W = rng.uniform(0.5, 1.5, (T, 2, n, N))
+    loss, dW = O.wbp_grad(llr, fr, u, T, W, multi=True)
+    eps = 1e-6
+    flat = W.reshape(-1)
+    bad = 0
+    for q in rng.choice(flat.size, size=60, replace=False):
+        wp = flat.copy(); wp[q] += eps
+        wm = flat.copy(); wm[q] -= eps
+        fd = (O.wbp_grad(llr, fr, u, T, wp, multi=True)[0] - O.wbp_grad(llr, fr, u, T, wm, multi=True)[0]) / (2 * eps)
+        if abs(fd - dW.reshape(-1)[q]) > 1e-6 + 1e-5 * abs(fd):
+            bad += 1
+    assert bad <= 1, bad
+
+
 def test_adam_first_step_closed_form():
     """Step 1: m_hat = g, v_hat = g^2, so each weight moves by lr g / (|g| + eps)."""
     rng = np.random.default_rng(1)
