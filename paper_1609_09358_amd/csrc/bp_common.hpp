@@ -33,7 +33,9 @@ __device__ __forceinline__ float g_ms(float a, float b) {
     return __uint_as_float(__float_as_uint(m) | s);
 }
 
-__device__ __forceinline__ float clipf(float v, float m) { return fminf(fmaxf(v, -m), m); }
+// clip to [-m, m] (m > 0) in one instruction: the median of v, -m and m is
+// min(max(v, -m), m) for every non-NaN v, signed zeros included
+__device__ __forceinline__ float clipf(float v, float m) { return __builtin_amdgcn_fmed3f(v, -m, m); }
 
 // The exact check-node rule of Sec. II-B, ln((1 + e^(a+b)) / (e^a + e^b)),
 // through the identity sgn(a) sgn(b) min(|a|,|b|) + ln(1 + e^-|a+b|) -
