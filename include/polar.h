@@ -139,7 +139,9 @@ polar_status polar_channel_awgn(const uint8_t* x, const float* z, const float* s
  * message computed in iteration t, direction d (0 = R, 1 = L), stage column s
  * (0-based, the stage that pairs i with i + 2^s) and output node i is
  * multiplied by weights[((t * 2 + d) * n + s) * N + i] before the addition and
- * the clipping (additions use one fused multiply-add).
+ * the clipping (additions use one fused multiply-add).  weight_layout = 1
+ * shares one weight among the nodes of a stage column: weights[(t * 2 + d) * n
+ * + s], [weight_iters][2][n] floats.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int32_t max_iter;      /* i_max >= 1 (Sec. III)                               */
@@ -151,6 +153,8 @@ typedef struct {
     int32_t weight_iters;  /* >= max_iter when weights != NULL                    */
     int32_t variant;       /* kernel layout: 0 automatic, else a value returned by
                               polar_bp_variants                                   */
+    int32_t weight_layout; /* 0 per node [iters][2][n][N], 1 per stage column
+                              [iters][2][n]                                       */
 } bp_params;
 
 /* llr    dev [B][N] channel LLRs (float32).

@@ -32,7 +32,8 @@ class polar_code_desc(C.Structure):
 
 class bp_params(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("stop", C.c_int32), ("llr_max", C.c_float), ("rule", C.c_int32),
-                ("weights", C.c_void_p), ("weight_iters", C.c_int32), ("variant", C.c_int32)]
+                ("weights", C.c_void_p), ("weight_iters", C.c_int32), ("variant", C.c_int32),
+                ("weight_layout", C.c_int32)]
 
 
 _lib = None
@@ -164,11 +165,13 @@ def polar_build_code(N, K, crc_bits=0, crc_poly=0, design_ebn0_db=2.0, frozen=No
 
 
 def make_bp_params(max_iter=100, stop=1, llr_max=20.0, weights=None, variant=0, rule=0):
+    """weights: [T][2][n][N] (one per node) or [T][2][n] (one per stage column)."""
     p = bp_params()
     p.max_iter, p.stop, p.llr_max, p.rule = int(max_iter), int(stop), float(llr_max), int(rule)
     p.weights = None if weights is None else weights.data_ptr()
     p.weight_iters = 0 if weights is None else int(weights.shape[0])
     p.variant = int(variant)
+    p.weight_layout = 1 if weights is not None and weights.dim() == 3 else 0
     return p
 
 
@@ -198,7 +201,8 @@ def bp_decode_batch(code: PolarCode, llr: torch.Tensor, max_iter=100, stop=1, ll
     B = llr.shape[0]
     _dev(llr, torch.float32, (B, code.N), "llr")
     if weights is not None:
-        _dev(weights, torch.float32, (weights.shape[0], 2, code.n, code.N), "weights")
+        _dev(weights, torch.float32, (weights.shape[0], 2, code.n) + ((code.N,) if weights.dim() == 4 else ()),
+             "weights")
     dev = llr.device
     if out is None:
         out = dict(u_hat=torch.empty((B, code.N), dtype=torch.uint8, device=dev),

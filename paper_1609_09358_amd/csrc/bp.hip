@@ -115,7 +115,7 @@ struct FrameIO {
 
 // Decode one frame: thread t of the frame's T threads, frame slot `slot` of
 // its wavefront (T < 64) or workgroup.  Returns the verdict (for queues).
-template <class G, bool WEIGHTED, bool SAVE, int RULE = 0>
+template <class G, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false>
 __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io, int max_iter, int stop, float lmax,
                                          const float* __restrict__ W, BpShared<G>& sh, int t, int slot) {
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
@@ -166,7 +166,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     bool gok = false, cok = false;
     float L0[V];
     while (true) {
-        const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * N : nullptr;
+        const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * (WSTAGE ? 1 : N) : nullptr;
         float* Sit = SAVE ? io.saved + (size_t)it * 2 * n * N : nullptr;
         // ---------------- R sweep: columns 0..n-1
         static_for<0, G::NWIN>([&](auto KC) {
@@ -185,8 +185,14 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float gi = g_rule<RULE>(r1, l2 + r2);
                     const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
-                        const float* w = Wit + (size_t)(0 * n + s) * N + ib;
-                        const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
+                        float wi, wj;
+                        if constexpr (WSTAGE) {
+                            wi = wj = Wit[0 * n + s];  // uniform: one scalar load
+                        } else {
+                            const float* w = Wit + (size_t)(0 * n + s) * N + ib;
+                            wi = w[v << G::wbase(k)];
+                            wj = w[v2 << G::wbase(k)];
+                        }
                         Rm[s + 1][v] = clipf(wi * gi, lmax);
                         Rm[s + 1][v2] = clipf(__fmaf_rn(wj, gj, r2), lmax);
                         if constexpr (SAVE) {
@@ -227,8 +233,14 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float gi = g_rule<RULE>(l1, l2 + r2);
                     const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
-                        const float* w = Wit + (size_t)(1 * n + s) * N + ib;
-                        const float wi = w[v << G::wbase(k)], wj = w[v2 << G::wbase(k)];
+                        float wi, wj;
+                        if constexpr (WSTAGE) {
+                            wi = wj = Wit[1 * n + s];
+                        } else {
+                            const float* w = Wit + (size_t)(1 * n + s) * N + ib;
+                            wi = w[v << G::wbase(k)];
+                            wj = w[v2 << G::wbase(k)];
+                        }
                         Lm[s][v] = clipf(wi * gi, lmax);
                         Lm[s][v2] = clipf(__fmaf_rn(wj, gj, l2), lmax);
                         if constexpr (SAVE) {
@@ -312,7 +324,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     return okv;
 }
 
-template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0>
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
     const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
@@ -332,7 +344,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     io.iters = iters_out ? iters_out + frame : nullptr;
     io.ok = ok_out ? ok_out + frame : nullptr;
     io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
-    bp_frame<G, WEIGHTED, SAVE, RULE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+    bp_frame<G, WEIGHTED, SAVE, RULE, WSTAGE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
 }
 
 // Persistent form for ragged batches: workgroups walk the list ids[0..*count)
@@ -380,7 +392,7 @@ using GatherFn = void (*)(CodeDev, const MixedIo*, const int32_t*, const int32_t
                           uint8_t*, int64_t, int32_t*, uint8_t*, int32_t*, int32_t*);
 
 struct Entry {
-    KernelFn plain, weighted, weighted_save, exact;
+    KernelFn plain, weighted, weighted_save, exact, weighted_stage;
     GatherFn gather_plain, gather_weighted;
     int wg, fpw;
 };
@@ -388,7 +400,8 @@ struct Entry {
 template <int NL, int RL>
 constexpr Entry make_entry() {
     return Entry{&bp_kernel<NL, RL, false, false>, &bp_kernel<NL, RL, true, false>, &bp_kernel<NL, RL, true, true>,
-                 &bp_kernel<NL, RL, false, false, 1>, &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
+                 &bp_kernel<NL, RL, false, false, 1>, &bp_kernel<NL, RL, true, false, 0, true>,
+                 &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
                  Geom<NL, RL>::FPW};
 }
 
@@ -439,7 +452,10 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
     if (B == 0) return POLAR_OK;
     const int64_t blocks = (B + e->fpw - 1) / e->fpw;
     if (blocks > (int64_t)INT32_MAX) return set_error(POLAR_ERR_INVALID_ARG, "bp: batch too large");
-    bp::KernelFn fn = p->rule == 1 ? e->exact : (p->weights ? e->weighted : e->plain);
+    bp::KernelFn fn = p->rule == 1 ? e->exact
+                      : !p->weights        ? e->plain
+                      : p->weight_layout   ? e->weighted_stage
+                                           : e->weighted;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
                        p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
     return hip_check(hipGetLastError(), "bp_kernel launch");
@@ -514,6 +530,8 @@ extern "C" polar_status bp_decode_batch(const polar_code* code, const float* llr
         return set_error(POLAR_ERR_UNSUPPORTED, "bp_decode_batch: the exact rule has no weighted form");
     if (p->weights && p->weight_iters < p->max_iter)
         return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: weight_iters < max_iter");
+    if (p->weight_layout != 0 && p->weight_layout != 1)
+        return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: weight_layout must be 0 or 1");
     if (p->variant != 0 && !bp_variant_supported(code->n, p->variant))
         return set_error(POLAR_ERR_INVALID_ARG, "bp_decode_batch: unknown variant");
     polar_status st = launch_bp(code, llr, B, p, u_hat, llr_u, iters, ok, stream);

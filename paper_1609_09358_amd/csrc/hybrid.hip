@@ -182,6 +182,7 @@ static polar_status check_bp_params(const polar_code* code, const bp_params* p) 
     if (p->rule != 0 && p->rule != 1) return set_error(POLAR_ERR_INVALID_ARG, "rule must be 0 or 1");
     if (p->rule == 1 && p->weights) return set_error(POLAR_ERR_UNSUPPORTED, "the exact rule has no weighted form");
     if (p->weights && p->weight_iters < p->max_iter) return set_error(POLAR_ERR_INVALID_ARG, "weight_iters < max_iter");
+    if (p->weight_layout != 0 && p->weight_layout != 1) return set_error(POLAR_ERR_INVALID_ARG, "weight_layout must be 0 or 1");
     if (p->variant != 0 && !bp_variant_supported(code->n, p->variant))
         return set_error(POLAR_ERR_INVALID_ARG, "unknown BP variant");
     return POLAR_OK;

@@ -108,11 +108,12 @@ def bp_fail_rate(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int,
     return 1.0 - float(o["ok"].float().mean())
 
 
-def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None):
+def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stage: bool = False):
     """Normalized min-sum: the single weight alpha (every g term scaled by it)
-    with the fewest BP failures on the frames `llr`; returns (W, alpha, rate)."""
+    with the fewest BP failures on the frames `llr`; returns (W, alpha, rate)
+    with W of shape [T][2][n][N], or [T][2][n] (one weight per stage column)."""
     grid = grid if grid is not None else [0.86 + 0.01 * i for i in range(15)]
-    shape = (T, 2, code.n, code.N)
+    shape = (T, 2, code.n) if per_stage else (T, 2, code.n, code.N)
     best = None
     for a in grid:
         W = torch.full(shape, float(a), dtype=torch.float32, device=llr.device)
@@ -123,24 +124,26 @@ def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None):
 
 
 def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factors=(0.96, 0.98, 1.02, 1.04),
-                  sweeps: int = 1):
+                  sweeps: int = 1, per_column: bool = False):
     """Coordinate search on the BP failure rate itself: each block of weights
-    (one iteration, one sweep direction) in turn is scaled by the factor that
-    lowers the failure rate on `llr` most, if any does.  Returns (W, rate)."""
+    -- one iteration and sweep direction, or (per_column) one iteration,
+    direction and stage column -- in turn is scaled by the factor that lowers
+    the failure rate on `llr` most, if any does.  Returns (W, rate)."""
     T = W.shape[0]
     cur = bp_fail_rate(code, llr, W, T)
+    blocks = [(t, d, s) for t in range(T) for d in range(2) for s in range(code.n)] if per_column else \
+             [(t, d) for t in range(T) for d in range(2)]
     for _ in range(sweeps):
-        for t in range(T):
-            for d in range(2):
-                base = W[t, d].clone()
-                best_f, best_r = None, cur
-                for f in factors:
-                    W[t, d] = base * f
-                    r = bp_fail_rate(code, llr, W, T)
-                    if r < best_r:
-                        best_f, best_r = f, r
-                W[t, d] = base if best_f is None else base * best_f
-                cur = best_r
+        for blk in blocks:
+            base = W[blk].clone()
+            best_f, best_r = None, cur
+            for f in factors:
+                W[blk] = base * f
+                r = bp_fail_rate(code, llr, W, T)
+                if r < best_r:
+                    best_f, best_r = f, r
+            W[blk] = base if best_f is None else base * best_f
+            cur = best_r
     return W, cur
 
 

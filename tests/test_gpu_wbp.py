@@ -179,3 +179,21 @@ def test_multi_loss_end_to_end_vs_oracle(T):
         l64, g64 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), multi=True)
         assert abs(tot - l64) <= 1e-5 * max(1.0, abs(l64))
         assert np.max(np.abs(g - g64)) <= 1e-4 * np.abs(g64).max()
+
+
+@pytest.mark.parametrize("N,K,c,T", [(64, 32, 0, 6), (1024, 512, 24, 12)])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_per_stage_weights_equal_expanded_per_node_weights(N, K, c, T, variant):
+    """One weight per stage column (scalar loads) decodes exactly like the
+    same weights repeated over the column's nodes, with early stopping."""
+    n = N.bit_length() - 1
+    code, u, llr = frames(N, K, c, 2.0, 40, seed=N + T + variant)
+    Ws = torch.from_numpy(np.random.default_rng(T).uniform(0.8, 1.1, (T, 2, n)).astype(np.float32)).cuda()
+    Wn = Ws[..., None].expand(T, 2, n, N).contiguous()
+    a = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=1, weights=Ws, variant=variant, soft=True)
+    b = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=1, weights=Wn, variant=variant, soft=True)
+    for key in ("u_hat", "llr_u", "iters", "ok"):
+        assert torch.equal(a[key], b[key]), key
+    ha = PB.HybridDecoder(code, max_iter=T, L=8, weights=Ws)(dev(llr))
+    hb = PB.HybridDecoder(code, max_iter=T, L=8, weights=Wn)(dev(llr))
+    assert torch.equal(ha["info"], hb["info"])
