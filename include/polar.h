@@ -227,6 +227,14 @@ polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, con
                                      hipStream_t stream_bp, hipStream_t stream_scl);
 polar_status polar_pipeline_workspace_size(const polar_code* code, int64_t B, int32_t L, const bp_params* params,
                                            size_t* bytes);
+/* Workgroups per CU the pipelined hybrid's BP may occupy at a time (1..64),
+ * or 0 (the default) for no limit.  With a limit, BP runs as a persistent grid
+ * of that many workgroups per CU (min-sum rule, no weights or one weight per
+ * stage column; other parameters ignore the limit), which leaves registers and
+ * LDS for the list decoder of the previous batch to run beside it.
+ * Process-wide; host only. */
+polar_status polar_set_pipeline_bp_occupancy(int32_t wgs_per_cu);
+int32_t polar_get_pipeline_bp_occupancy(void);
 
 /* ---------------------------------------------------------------------------
  * Ragged batches that mix several codes (block lengths and rates): the

@@ -108,3 +108,23 @@ def tune_mixed(codes, llr_per_code, max_iter: int, L: int, scl_frames: int = 204
     b = tune_scl_budget(codes[c_big], sub, L)
     detail["scl"] = b
     return {"variants": variants, "budget": b["budget"], "detail": detail}
+
+
+def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=(0, 4, 6, 8), steps: int = 6) -> dict:
+    """Time the two-stream hybrid over `steps` batches of `llr` for each cap on
+    BP workgroups per CU (polar_set_pipeline_bp_occupancy; 0 = none) and leave
+    the fastest set.  Returns {"wgs_per_cu": best, "ms": {cap: ms per batch}}."""
+    import time
+    timings = {}
+    out = [dict(info=torch.empty((llr.shape[0], pipe.code.K), dtype=torch.uint8, device=llr.device))]
+    for c in choices:
+        PB.polar_set_pipeline_bp_occupancy(c)
+        pipe([llr] * 2, outs=out * 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pipe([llr] * steps, outs=out * steps)
+        torch.cuda.synchronize()
+        timings[c] = (time.perf_counter() - t0) / steps * 1e3
+    best = min(timings, key=timings.get)
+    PB.polar_set_pipeline_bp_occupancy(best)
+    return {"wgs_per_cu": int(best), "ms": {int(k): round(v, 4) for k, v in timings.items()}}

@@ -69,6 +69,7 @@ def lib():
             "wbp_bce_multi": [vp, vp, vp, i64, i32, C.c_double, vp, vp, vp],
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "polar_set_scl_lds_budget": [i64],
+            "polar_set_pipeline_bp_occupancy": [i32],
             "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
             "polar_pipeline_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
             "polar_mixed_create": [vp, i32, i64, C.POINTER(bp_params), i32, vp, C.POINTER(vp)],
@@ -79,6 +80,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.polar_get_pipeline_bp_occupancy.argtypes = []
+        L.polar_get_pipeline_bp_occupancy.restype = i32
         L.polar_get_scl_lds_budget.argtypes = []
         L.polar_get_scl_lds_budget.restype = i64
         L.polar_mixed_free.argtypes = [vp]
@@ -237,6 +240,15 @@ def polar_set_scl_lds_budget(nbytes: int):
 
 def polar_get_scl_lds_budget() -> int:
     return int(lib().polar_get_scl_lds_budget())
+
+
+def polar_set_pipeline_bp_occupancy(wgs_per_cu: int):
+    """BP workgroups per CU in the pipelined hybrid (0 = no limit); process-wide."""
+    _check(lib().polar_set_pipeline_bp_occupancy(int(wgs_per_cu)))
+
+
+def polar_get_pipeline_bp_occupancy() -> int:
+    return int(lib().polar_get_pipeline_bp_occupancy())
 
 
 def scl_decode_batch(code: PolarCode, llr: torch.Tensor, L, frame_ids=None, out=None, workspace=None):
@@ -491,5 +503,6 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
-            "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_mixed_create", "polar_mixed_decode",
+            "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
+            "polar_get_pipeline_bp_occupancy", "polar_mixed_create", "polar_mixed_decode",
             "polar_mixed_decode_graph", "polar_mixed_free"]

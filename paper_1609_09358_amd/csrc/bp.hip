@@ -324,7 +324,9 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     return okv;
 }
 
-template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false>
+// PERSIST: a grid smaller than the batch walks it (frame slots advance by the
+// grid size), so a capped grid leaves room on every CU for other kernels.
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false, bool PERSIST = false>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
     const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
@@ -335,16 +337,21 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
     const int tid = threadIdx.x;
     const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
     const int slot = (G::T < 64) ? (tid >> G::P) : 0;
-    const int64_t frame = (int64_t)blockIdx.x * G::FPW + slot;
-    if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
-    FrameIO io;
-    io.llr = llr + frame * N;
-    io.u_hat = u_hat ? u_hat + frame * N : nullptr;
-    io.llr_u = llr_u ? llr_u + frame * N : nullptr;
-    io.iters = iters_out ? iters_out + frame : nullptr;
-    io.ok = ok_out ? ok_out + frame : nullptr;
-    io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
-    bp_frame<G, WEIGHTED, SAVE, RULE, WSTAGE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+    const int64_t stride = PERSIST ? (int64_t)gridDim.x * G::FPW : 0;
+    for (int64_t f0 = (int64_t)blockIdx.x * G::FPW; f0 < B; f0 += stride) {
+        const int64_t frame = f0 + slot;
+        if (PERSIST && G::T >= 64 && f0 != (int64_t)blockIdx.x * G::FPW) __syncthreads();  // staging reuse
+        if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
+        FrameIO io;
+        io.llr = llr + frame * N;
+        io.u_hat = u_hat ? u_hat + frame * N : nullptr;
+        io.llr_u = llr_u ? llr_u + frame * N : nullptr;
+        io.iters = iters_out ? iters_out + frame : nullptr;
+        io.ok = ok_out ? ok_out + frame : nullptr;
+        io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
+        bp_frame<G, WEIGHTED, SAVE, RULE, WSTAGE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        if (!PERSIST) break;
+    }
 }
 
 // Persistent form for ragged batches: workgroups walk the list ids[0..*count)
@@ -393,6 +400,7 @@ using GatherFn = void (*)(CodeDev, const MixedIo*, const int32_t*, const int32_t
 
 struct Entry {
     KernelFn plain, weighted, weighted_save, exact, weighted_stage;
+    KernelFn persist_plain, persist_weighted_stage;
     GatherFn gather_plain, gather_weighted;
     int wg, fpw;
 };
@@ -401,6 +409,7 @@ template <int NL, int RL>
 constexpr Entry make_entry() {
     return Entry{&bp_kernel<NL, RL, false, false>, &bp_kernel<NL, RL, true, false>, &bp_kernel<NL, RL, true, true>,
                  &bp_kernel<NL, RL, false, false, 1>, &bp_kernel<NL, RL, true, false, 0, true>,
+                 &bp_kernel<NL, RL, false, false, 0, false, true>, &bp_kernel<NL, RL, true, false, 0, true, true>,
                  &bp_gather_kernel<NL, RL, false>, &bp_gather_kernel<NL, RL, true>, Geom<NL, RL>::WG,
                  Geom<NL, RL>::FPW};
 }
@@ -445,7 +454,7 @@ int bp_list_variants(int n, int32_t* ids, int cap) {
 }
 
 polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p, uint8_t* u_hat,
-                       float* llr_u, int32_t* iters, uint8_t* ok, hipStream_t stream) {
+                       float* llr_u, int32_t* iters, uint8_t* ok, hipStream_t stream, int wgs_per_cu) {
     const int variant = p->variant ? p->variant : bp_default_variant(code->n);
     const bp::Entry* e = bp::lookup(code->n, variant);
     if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "bp: no kernel variant for this block length");
@@ -456,7 +465,16 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
                       : !p->weights        ? e->plain
                       : p->weight_layout   ? e->weighted_stage
                                            : e->weighted;
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
+    int64_t grid = blocks;
+    if (wgs_per_cu > 0 && p->rule == 0 && (!p->weights || p->weight_layout == 1)) {
+        // capped persistent grid: leaves room on every CU for concurrent kernels
+        const int64_t cap = (int64_t)device_cu_count() * wgs_per_cu;
+        if (cap < blocks) {
+            fn = p->weights ? e->persist_weighted_stage : e->persist_plain;
+            grid = cap;
+        }
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
                        p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
     return hip_check(hipGetLastError(), "bp_kernel launch");
 }

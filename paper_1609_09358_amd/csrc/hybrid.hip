@@ -5,6 +5,8 @@
 // verdict is not ok into a device queue ("copy failed CWs to buffer"),
 // persistent CA-SCL workgroups that read the queue length on the device, and
 // a merge that emits the information bits and statistics.
+#include <atomic>
+
 #include "internal.hpp"
 
 namespace polarhip {
@@ -127,6 +129,9 @@ size_t carve(const polar_code* code, int64_t B, const SclPlan& plan, void* base,
     return off;
 }
 
+// BP workgroups per CU in the pipelined hybrid (0: no limit)
+std::atomic<int> g_pipe_bp_wgs{0};
+
 // four events (BP done and SCL done, per slot) of the calling thread on the
 // current device, created on first use and kept: a later call re-records them
 // after every wait that an earlier call enqueued on them
@@ -147,8 +152,8 @@ polar_status pipeline_events(hipEvent_t** out) {
 
 // BP and compaction of one batch on `stream`
 polar_status enqueue_bp_part(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
-                             const HybridWs& w, hipStream_t stream) {
-    polar_status st = launch_bp(code, llr, B, p, w.u_hat, nullptr, w.iters, w.ok, stream);
+                             const HybridWs& w, hipStream_t stream, int wgs_per_cu = 0) {
+    polar_status st = launch_bp(code, llr, B, p, w.u_hat, nullptr, w.iters, w.ok, stream, wgs_per_cu);
     if (st != POLAR_OK) return st;
     hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, stream, w.count);
     const unsigned cblocks = (unsigned)((B + 255) / 256);
@@ -262,7 +267,7 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
     for (int64_t j = 0; j < nbatch && st == POLAR_OK; ++j) {
         const int s = (int)(j & 1);
         if (j >= 2) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[s], 0), "stream wait");
-        if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], stream_bp);
+        if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], stream_bp, g_pipe_bp_wgs.load());
         if (st == POLAR_OK) st = hip_check(hipEventRecord(bp_done[s], stream_bp), "event record");
         if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_scl, bp_done[s], 0), "stream wait");
         if (st == POLAR_OK)
@@ -273,3 +278,12 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
     if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[(nbatch - 1) & 1], 0), "stream wait");
     return st == POLAR_OK ? ok_status() : st;
 }
+
+extern "C" polar_status polar_set_pipeline_bp_occupancy(int32_t wgs_per_cu) {
+    if (wgs_per_cu < 0 || wgs_per_cu > 64)
+        return set_error(POLAR_ERR_INVALID_ARG, "polar_set_pipeline_bp_occupancy: must be in [0, 64]");
+    g_pipe_bp_wgs.store(wgs_per_cu);
+    return ok_status();
+}
+
+extern "C" int32_t polar_get_pipeline_bp_occupancy(void) { return g_pipe_bp_wgs.load(); }

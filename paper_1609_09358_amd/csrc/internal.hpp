@@ -64,9 +64,12 @@ polar_status ok_status();
 polar_status hip_check(hipError_t e, const char* what);
 
 // launch helpers implemented in the kernel translation units
+// wgs_per_cu > 0: at most that many BP workgroups per CU at a time (a
+// persistent grid), where such a kernel exists (min-sum, unweighted or
+// per-stage weights); otherwise one workgroup per frame group
 polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
                        uint8_t* u_hat, float* llr_u, int32_t* iters, uint8_t* ok,
-                       hipStream_t stream);
+                       hipStream_t stream, int wgs_per_cu = 0);
 polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,
                             const float* W, int variant, uint8_t* u_hat, float* llr_u, uint8_t* ok, float* saved,
                             hipStream_t stream);

@@ -82,6 +82,17 @@ def test_scl_lds_budget_setter():
     assert PB.polar_get_scl_lds_budget() == 0
 
 
+def test_pipeline_bp_occupancy_setter():
+    lib = PB.lib()
+    assert PB.polar_get_pipeline_bp_occupancy() == 0
+    assert lib.polar_set_pipeline_bp_occupancy(-1) == 1
+    assert lib.polar_set_pipeline_bp_occupancy(65) == 1
+    PB.polar_set_pipeline_bp_occupancy(6)
+    assert PB.polar_get_pipeline_bp_occupancy() == 6
+    PB.polar_set_pipeline_bp_occupancy(0)
+    assert PB.polar_get_pipeline_bp_occupancy() == 0
+
+
 def test_bp_variants_query():
     assert PB.polar_bp_variants(1024) == [2, 3]
     assert PB.polar_bp_variants(8) == [2, 3]

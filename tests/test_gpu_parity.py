@@ -353,3 +353,22 @@ def test_decision_aided_hybrid_bit_exact_vs_f32_oracle():
     assert np.array_equal(host(out["used_scl"]), ref["used_scl"])
     assert np.array_equal(host(out["info"]), ref["info"])
     assert 0 < ref["used_scl"].sum() < B
+
+
+@pytest.mark.parametrize("occ", [1, 3, 8])
+def test_pipelined_hybrid_with_capped_bp_grid(occ):
+    """With the BP grid capped (persistent BP walking the batch), every batch
+    still decodes exactly as the single-stream hybrid; plain and per-stage
+    weighted BP, and a block length whose frames share a wavefront."""
+    PB.polar_set_pipeline_bp_occupancy(occ)
+    try:
+        for N, K, c, w in ((1024, 512, 16, False), (1024, 512, 24, True), (128, 64, 8, False)):
+            n = N.bit_length() - 1
+            code, info, u, x, llr = frames(N, K, c, 2.5, 2.0, 700, seed=N + occ)
+            W = torch.full((20, 2, n), 0.94, device="cuda") if w else None
+            ref = PB.HybridDecoder(code, max_iter=20, L=8, weights=W)(dev(llr))
+            outs = PB.HybridPipeline(code, max_iter=20, L=8, weights=W)([dev(llr)] * 3)
+            for o in outs:
+                assert torch.equal(o["info"], ref["info"])
+    finally:
+        PB.polar_set_pipeline_bp_occupancy(0)
