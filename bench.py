@@ -300,6 +300,8 @@ def main():
 
     extra["c3_mixed"] = c3_mixed(args.steps)
     extra["c4_learned_bp"] = c4_learned_bp(frames=args.train_frames)
+    extra["scl_ranking_ab"] = scl_ranking_ab(code, llr, bp_out, W, T)
+    extra["latency"] = latency_study(code, learned, T, W)
     extra["c2_rules"] = c2_rules(args.frames, max(3, args.steps // 4))
     extra["paper_operating_point"] = paper_operating_point()
 
@@ -335,6 +337,60 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line))
+
+
+def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
+    """List decoding with the pruned pseudo sort against a bitonic sort of the
+    candidates (Sec. II-A describes both), on the frames the learned BP failed
+    in one batch (latency-bound) and on 8192 frames (throughput-bound)."""
+    import torch
+
+    from paper_1609_09358_amd import binding as PB
+
+    fail = torch.nonzero(bp_out["ok"] == 0).flatten().to(torch.int32).contiguous()
+    many = torch.arange(8192, dtype=torch.int32, device="cuda")
+    res = {}
+    for L in (8, 32):
+        for name, ids in (("failed_frames", fail), ("8192_frames", many)):
+            row = {}
+            for mode in (1, 2):
+                PB.polar_set_scl_ranking(mode)
+                out = PB.scl_decode_batch(code, llr, L, frame_ids=ids)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    PB.scl_decode_batch(code, llr, L, frame_ids=ids, out=out)
+                torch.cuda.synchronize()
+                row["bitonic_ms" if mode == 2 else "pseudo_sort_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+            res[f"L{L}_{name}"] = dict(frames=int(ids.numel()), **row)
+    PB.polar_set_scl_ranking(0)
+    return res
+
+
+def latency_study(code, learned, T, W, reps=20):
+    """Decode-call latency of the learned hybrid (the latency of every frame
+    in the call) for small batches over Eb/N0, median and worst over `reps`
+    calls, in the spirit of the paper's latency figure."""
+    import torch
+
+    from paper_1609_09358_amd import train_wbp as TW
+
+    gen = TW.Trainer(code, 1, 16, seed=5555)
+    rows = []
+    for e in (1.5, 2.5, 3.5):
+        for B in (1, 64, 4096):
+            _, _, llr = gen.frames(B, ebn0=e)
+            out = learned(llr)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                learned(llr, out=out)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            ts.sort()
+            rows.append({"ebn0_db": e, "frames": B, "median_ms": round(ts[len(ts) // 2], 3), "worst_ms": round(ts[-1], 3)})
+    return rows
 
 
 def c4_learned_bp(frames=1_000_000, batch=4096, eval_frames=100_000):

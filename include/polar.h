@@ -286,6 +286,16 @@ polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,
 polar_status polar_set_scl_lds_budget(int64_t bytes);
 int64_t polar_get_scl_lds_budget(void);
 
+/* How the list decoder picks the L survivors among the 2L candidates (Sec.
+ * II-A describes both): 1 the pruned pseudo sort -- each candidate counts the
+ * candidates before it; 2 a bitonic sort of the candidates across the
+ * wavefront (list sizes 8 and 32, N >= 32; other lists use the pseudo sort);
+ * 0 (default) automatic: the bitonic sort for L = 32, where it measured faster
+ * on MI355X, the pseudo sort otherwise.  Both use the strict order (metric,
+ * parent position, bit), so results are identical.  Process-wide; host only. */
+polar_status polar_set_scl_ranking(int32_t mode);
+int32_t polar_get_scl_ranking(void);
+
 /* ---------------------------------------------------------------------------
  * Weighted (learned) min-sum BP -- not in the paper; trains the weights of the
  * weighted form of bp_decode_batch.  W: dev float [T][2][n][N] as in bp_params.

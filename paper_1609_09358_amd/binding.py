@@ -70,6 +70,7 @@ def lib():
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "polar_set_scl_lds_budget": [i64],
             "polar_set_pipeline_bp_occupancy": [i32],
+            "polar_set_scl_ranking": [i32],
             "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
             "polar_pipeline_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
             "polar_mixed_create": [vp, i32, i64, C.POINTER(bp_params), i32, vp, C.POINTER(vp)],
@@ -80,6 +81,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.polar_get_scl_ranking.argtypes = []
+        L.polar_get_scl_ranking.restype = i32
         L.polar_get_pipeline_bp_occupancy.argtypes = []
         L.polar_get_pipeline_bp_occupancy.restype = i32
         L.polar_get_scl_lds_budget.argtypes = []
@@ -240,6 +243,15 @@ def polar_set_scl_lds_budget(nbytes: int):
 
 def polar_get_scl_lds_budget() -> int:
     return int(lib().polar_get_scl_lds_budget())
+
+
+def polar_set_scl_ranking(mode: int):
+    """List decoder survivor selection: 0 automatic, 1 pruned pseudo sort, 2 bitonic sort."""
+    _check(lib().polar_set_scl_ranking(int(mode)))
+
+
+def polar_get_scl_ranking() -> int:
+    return int(lib().polar_get_scl_ranking())
 
 
 def polar_set_pipeline_bp_occupancy(wgs_per_cu: int):
@@ -504,5 +516,5 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
-            "polar_get_pipeline_bp_occupancy", "polar_mixed_create", "polar_mixed_decode",
+            "polar_get_pipeline_bp_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",
             "polar_mixed_decode_graph", "polar_mixed_free"]

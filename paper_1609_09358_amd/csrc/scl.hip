@@ -140,6 +140,28 @@ __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float m
     return rank;
 }
 
+// Bitonic sort of the candidates across the wavefront (the alternative to the
+// pruned pseudo sort that Sec. II-A also describes): keys (metric bits, lane)
+// in the same strict order as candidate_rank, lanes without a candidate last;
+// after the network lane p holds the key of rank p, i.e. the candidate it takes.
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    return (uint64_t)__shfl_xor((unsigned long long)v, m, 64);
+}
+
+__device__ __forceinline__ int bitonic_select(float met, int ncand, int lane) {
+    uint64_t key = lane < ncand ? (((uint64_t)__float_as_uint(met) << 32) | (uint64_t)lane) : ~0ull;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t o = shfl_xor64(key, j);
+            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+            key = keep_min ? (o < key ? o : key) : (o > key ? o : key);
+        }
+    }
+    return (int)(key & 63u);
+}
+
 struct Layout {
     int gl;      // LLR levels < gl in LDS, the others in the workgroup's global slice
     int sl;      // LDS floats per slot: levels BL..gl-1, level d at offset 2^d - 2^BL, padded
@@ -152,7 +174,7 @@ struct Layout {
     int64_t u_stride;  // u_hat row stride of a ragged batch
 };
 
-template <int L, int BL>
+template <int L, int BL, bool BITONIC = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
@@ -339,12 +361,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     const float pmp = __shfl(PM, p, 64);
                     const float pen = (b != (lp < 0.0f ? 1 : 0)) ? fabsf(lp) : 0.0f;
                     const float met = pmp + pen;
-                    const int rank = candidate_rank<L>(mets, ncand, met, lane);
                     const int nact = ncand < L ? ncand : L;
-                    // each candidate pushes its lane to the lane of its rank (ranks
-                    // are distinct; lanes without a candidate push to themselves,
-                    // above every rank), so lane l receives the candidate of rank l
-                    const int c = __builtin_amdgcn_ds_permute((lane < ncand ? rank : lane) << 2, lane);
+                    int c;
+                    if constexpr (BITONIC) {
+                        c = bitonic_select(met, ncand, lane);
+                    } else {
+                        const int rank = candidate_rank<L>(mets, ncand, met, lane);
+                        // each candidate pushes its lane to the lane of its rank (ranks
+                        // are distinct; lanes without a candidate push to themselves,
+                        // above every rank), so lane l receives the candidate of rank l
+                        c = __builtin_amdgcn_ds_permute((lane < ncand ? rank : lane) << 2, lane);
+                    }
                     const int par = c >> 1;
                     const uint32_t cb = (uint32_t)(c & 1);
                     const uint32_t syn_i = code.syn[i];
@@ -467,8 +494,13 @@ KernelFn pick_bl(int bl) {
     }
 }
 
-KernelFn pick(int L, int n) {
+// bitonic ranking: instantiated for the list sizes the comparisons use, BL = 5
+KernelFn pick(int L, int n, bool bitonic = false) {
     const int bl = n < 5 ? n : 5;
+    if (bitonic && bl == 5) {
+        if (L == 8) return &scl_kernel<8, 5, true>;
+        if (L == 32) return &scl_kernel<32, 5, true>;
+    }
     switch (L) {
         case 1: return pick_bl<1>(bl);
         case 2: return pick_bl<2>(bl);
@@ -519,6 +551,15 @@ LdsPlan lds_plan(int L, int N, int n, int k, int gl, bool tg) {
 
 }  // namespace scl
 
+// candidate ranking: 0 automatic (the bitonic sort where it measured faster:
+// L = 32), 1 pruned pseudo sort (counting), 2 bitonic sort
+static std::atomic<int> g_scl_rank_mode{0};
+
+static bool use_bitonic(int L) {
+    const int m = g_scl_rank_mode.load(std::memory_order_relaxed);
+    return m == 2 || (m == 0 && L == 32);
+}
+
 // LDS per workgroup; 0 (automatic) divides a CU's 160 KB among as many
 // one-wave workgroups as the kernel's registers allow on a CU
 static std::atomic<int64_t> g_scl_lds_budget{0};
@@ -526,7 +567,7 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan) {
     const int n = code->n, N = code->N, k = code->k;
-    scl::KernelFn fn = scl::pick(L, n);
+    scl::KernelFn fn = scl::pick(L, n, use_bitonic(L));
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
     const int gl_min = n < 6 ? n : 6;
     // everything in LDS if it fits; otherwise the trace goes to the global
@@ -569,7 +610,7 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host, uint8_t* u_hat,
                         uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream, const MixedIo* io,
                         int64_t u_stride) {
-    scl::KernelFn fn = scl::pick(L, code->n);
+    scl::KernelFn fn = scl::pick(L, code->n, use_bitonic(L));
     scl::Layout lay;
     lay.gl = plan.gl;
     lay.sl = scl::slot_floats(code->n, plan.gl);
@@ -614,3 +655,11 @@ extern "C" polar_status polar_set_scl_lds_budget(int64_t bytes) {
 }
 
 extern "C" int64_t polar_get_scl_lds_budget(void) { return g_scl_lds_budget.load(std::memory_order_relaxed); }
+
+extern "C" polar_status polar_set_scl_ranking(int32_t mode) {
+    if (mode < 0 || mode > 2) return set_error(POLAR_ERR_INVALID_ARG, "polar_set_scl_ranking: mode must be 0, 1 or 2");
+    g_scl_rank_mode.store(mode, std::memory_order_relaxed);
+    return ok_status();
+}
+
+extern "C" int32_t polar_get_scl_ranking(void) { return g_scl_rank_mode.load(std::memory_order_relaxed); }

@@ -93,6 +93,16 @@ def test_pipeline_bp_occupancy_setter():
     assert PB.polar_get_pipeline_bp_occupancy() == 0
 
 
+def test_scl_ranking_setter():
+    lib = PB.lib()
+    assert PB.polar_get_scl_ranking() == 0
+    assert lib.polar_set_scl_ranking(3) == 1
+    assert lib.polar_set_scl_ranking(-1) == 1
+    PB.polar_set_scl_ranking(2)
+    assert PB.polar_get_scl_ranking() == 2
+    PB.polar_set_scl_ranking(0)
+
+
 def test_bp_variants_query():
     assert PB.polar_bp_variants(1024) == [2, 3]
     assert PB.polar_bp_variants(8) == [2, 3]

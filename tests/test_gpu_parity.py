@@ -372,3 +372,72 @@ def test_pipelined_hybrid_with_capped_bp_grid(occ):
                 assert torch.equal(o["info"], ref["info"])
     finally:
         PB.polar_set_pipeline_bp_occupancy(0)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("N,K,c,L", [(64, 24, 8, 8), (1024, 512, 24, 32), (2048, 1024, 16, 8), (256, 120, 8, 32)])
+def test_ranking_modes_bit_exact(N, K, c, L, mode):
+    """The bitonic-sort and the pseudo-sort survivor selections both decode
+    exactly as the oracle (same strict order), whichever the default picks."""
+    B = 9
+    code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, B, seed=17 * N + L)
+    ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32")
+    PB.polar_set_scl_ranking(mode)
+    try:
+        out = PB.scl_decode_batch(code, dev(llr), L)
+        uh, ok, pm = host(out["u_hat"]), host(out["crc_ok"]), host(out["pm"])
+    finally:
+        PB.polar_set_scl_ranking(0)
+    assert np.array_equal(ok, ref["crc_ok"])
+    assert np.array_equal(pm, ref["pm"].astype(np.float32))
+    assert np.array_equal(uh, ref["u_hat"])
+
+
+# ------------------------------------------------------------------ the benchmark's configurations at full size
+
+def test_plain_bp_c1_configuration_bit_exact():
+    """N = 128, K = 64, no CRC, GA at 2 dB, 1000 frames at 2 dB, min-sum BP with
+    at most 100 iterations and the re-encoding stop: every frame against the
+    oracle's float build."""
+    N, K, c, B = 128, 64, 0, 1000
+    code = PB.PolarCode(N, K, c, 0, 2.0)
+    info = inputs.info_bits(B, K, seed=1)
+    _, x = O.encode_batch(info, K, c, 0, code.frozen)
+    llr = O.channel_llr(x, inputs.noise(B, N, seed=1), O.sigma2(2.0, K / N))
+    out = PB.bp_decode_batch(code, dev(llr), max_iter=100, stop=1)
+    ref = O.bp_batch(llr, code.frozen, c, 0, max_iter=100, stop=1, prec="f32")
+    assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
+    assert np.array_equal(host(out["iters"]), ref["iters"])
+    assert np.array_equal(host(out["ok"]), ref["ok"])
+
+
+def test_learned_hybrid_full_size_pipelined_sampled():
+    """The benchmark's learned hybrid at its full size and launch path: 65536
+    frames at 2.5 dB through the two-stream pipeline, weighted BP T = 20 with one
+    weight per stage column, CA-SCL L = 32 with 256 decision-aided positions,
+    CRC-24; sampled frames (list-decoded ones included) against the oracle's
+    float build with the same weights."""
+    N, K, c, L, T, B = 1024, 512, 24, 32, 20, 65536
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=256)
+    info = inputs.info_bits(B, K, seed=2025)
+    x = PB.polar_encode(code, dev(info))
+    s2 = torch.full((B,), O.sigma2(2.5, 0.5), dtype=torch.float32, device="cuda")
+    llr = PB.polar_channel_awgn(x, dev(inputs.noise(B, N, seed=2025, dtype=np.float32)), s2)
+    rng = np.random.default_rng(3)
+    Ws = (0.94 * rng.uniform(0.97, 1.03, (T, 2, 10))).astype(np.float32)
+    W = dev(Ws)
+    pipe = PB.HybridPipeline(code, max_iter=T, L=L, weights=W)
+    outs = pipe([llr, llr], want_used=True)
+    torch.cuda.synchronize()
+    a, b = host(outs[0]["info"]), host(outs[1]["info"])
+    used = host(outs[0]["used_scl"])
+    assert np.array_equal(a, b)
+    pick = np.concatenate([rng.choice(np.where(used == 1)[0], size=12, replace=False),
+                           rng.choice(B, size=36, replace=False)])
+    llr_s = host(llr[torch.from_numpy(pick).cuda()])
+    Wn = np.repeat(Ws[..., None], N, axis=3).astype(np.float64)
+    ref = O.hybrid_batch(llr_s, code.frozen, K, c, POLY[c], T, L, W=Wn, prec="f32", da=code.decision_aided)
+    assert np.array_equal(a[pick], ref["info"])
+    assert np.array_equal(used[pick], ref["used_scl"])
+    assert 0.005 < used.mean() < 0.2
+    assert np.mean(np.any(a != info, axis=1)) < 1e-3
