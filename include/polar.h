@@ -211,9 +211,10 @@ polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64
  * scheduling of Sec. III (Fig. 3) on two streams.  For batch j, BP and the
  * compaction of its failed frames run on stream_bp; its CA-SCL and the merge
  * run on stream_scl once they are done, so the list decoding of batch j
- * overlaps the BP of batch j + 1.  Per-batch state is double buffered in the
- * workspace (batch j + 2 waits for the merge of batch j); the list decoder's
- * global slice is shared, since list decodes follow one another on stream_scl.
+ * overlaps the BP of the following batches.  The workspace holds two
+ * per-batch states (batch j + 2 waits for the merge of batch j); the list
+ * decoder's global slice is shared, since list decodes follow one another on
+ * stream_scl.
  * llr, info_hat, used_scl: host arrays of nbatch device pointers ([B][N],
  * [B][K], [B]; used_scl may be NULL or hold NULL entries); batches may share
  * an input buffer.  Results and stats (accumulated as in hybrid_decode_batch)

@@ -132,17 +132,23 @@ size_t carve(const polar_code* code, int64_t B, const SclPlan& plan, void* base,
 // BP workgroups per CU in the pipelined hybrid (0: no limit)
 std::atomic<int> g_pipe_bp_wgs{0};
 
-// four events (BP done and SCL done, per slot) of the calling thread on the
+// per-batch states in flight in the pipelined hybrid: batch j + kPipeSlots
+// reuses batch j's state, so its BP waits for batch j's merge (three states
+// measured no faster than two: the list decoder and the next BP compete for
+// the same CUs, not for the state)
+constexpr int kPipeSlots = 2;
+
+// the events (BP done and SCL done, per slot) of the calling thread on the
 // current device, created on first use and kept: a later call re-records them
 // after every wait that an earlier call enqueued on them
 polar_status pipeline_events(hipEvent_t** out) {
     constexpr int kMaxDev = 64;
-    thread_local hipEvent_t ev[kMaxDev][4] = {};
+    thread_local hipEvent_t ev[kMaxDev][2 * kPipeSlots] = {};
     int dev = 0;
     polar_status st = hip_check(hipGetDevice(&dev), "get device");
     if (st != POLAR_OK) return st;
     if (dev < 0 || dev >= kMaxDev) return set_error(POLAR_ERR_UNSUPPORTED, "device index out of range");
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2 * kPipeSlots; ++i)
         if (!ev[dev][i] &&
             (st = hip_check(hipEventCreateWithFlags(&ev[dev][i], hipEventDisableTiming), "event create")) != POLAR_OK)
             return st;
@@ -210,7 +216,7 @@ extern "C" polar_status polar_pipeline_workspace_size(const polar_code* code, in
     SclPlan plan;
     polar_status st = scl_plan(code, L, B > 0 ? B : 1, &plan);
     if (st != POLAR_OK) return st;
-    *bytes = carve(code, B, plan, nullptr, nullptr, 2);
+    *bytes = carve(code, B, plan, nullptr, nullptr, kPipeSlots);
     return ok_status();
 }
 
@@ -251,22 +257,22 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
     if (st != POLAR_OK) return st;
     SclPlan plan;
     if ((st = scl_plan(code, L, B > 0 ? B : 1, &plan)) != POLAR_OK) return st;
-    const size_t need = carve(code, B, plan, nullptr, nullptr, 2);
+    const size_t need = carve(code, B, plan, nullptr, nullptr, kPipeSlots);
     if (!ws || ws_bytes < need) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_pipelined: workspace too small");
     if (nbatch == 0 || B == 0) return ok_status();
-    HybridWs w[2];
-    carve(code, B, plan, ws, w, 2);
+    HybridWs w[kPipeSlots];
+    carve(code, B, plan, ws, w, kPipeSlots);
     hipEvent_t* ev = nullptr;
     if ((st = pipeline_events(&ev)) != POLAR_OK) return st;
     hipEvent_t* bp_done = ev;
-    hipEvent_t* scl_done = ev + 2;
+    hipEvent_t* scl_done = ev + kPipeSlots;
     // the first batches must not start before work already queued on stream_scl
     // has finished with the shared list-decoder slice of an earlier call
     if (st == POLAR_OK) st = hip_check(hipEventRecord(scl_done[0], stream_scl), "event record");
     if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[0], 0), "stream wait");
     for (int64_t j = 0; j < nbatch && st == POLAR_OK; ++j) {
-        const int s = (int)(j & 1);
-        if (j >= 2) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[s], 0), "stream wait");
+        const int s = (int)(j % kPipeSlots);
+        if (j >= kPipeSlots) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[s], 0), "stream wait");
         if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], stream_bp, g_pipe_bp_wgs.load());
         if (st == POLAR_OK) st = hip_check(hipEventRecord(bp_done[s], stream_bp), "event record");
         if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_scl, bp_done[s], 0), "stream wait");
@@ -275,7 +281,8 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
                                   stats, stream_scl);
         if (st == POLAR_OK) st = hip_check(hipEventRecord(scl_done[s], stream_scl), "event record");
     }
-    if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[(nbatch - 1) & 1], 0), "stream wait");
+    if (st == POLAR_OK)
+        st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[(int)((nbatch - 1) % kPipeSlots)], 0), "stream wait");
     return st == POLAR_OK ? ok_status() : st;
 }
 
