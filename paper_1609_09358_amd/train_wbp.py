@@ -108,6 +108,13 @@ def bp_fail_rate(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int,
     return 1.0 - float(o["ok"].float().mean())
 
 
+def bp_cost(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int, fail_weight: float) -> float:
+    """Mean BP iterations (a failed frame counts its T) plus fail_weight times
+    the failure rate: a proxy for the hybrid's time per frame."""
+    o = PB.bp_decode_batch(code, llr, max_iter=T, stop=1, weights=W)
+    return float(o["iters"].float().mean()) + fail_weight * (1.0 - float(o["ok"].float().mean()))
+
+
 def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stage: bool = False):
     """Normalized min-sum: the single weight alpha (every g term scaled by it)
     with the fewest BP failures on the frames `llr`; returns (W, alpha, rate)
@@ -124,13 +131,16 @@ def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stag
 
 
 def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factors=(0.96, 0.98, 1.02, 1.04),
-                  sweeps: int = 1, per_column: bool = False):
-    """Coordinate search on the BP failure rate itself: each block of weights
-    -- one iteration and sweep direction, or (per_column) one iteration,
-    direction and stage column -- in turn is scaled by the factor that lowers
-    the failure rate on `llr` most, if any does.  Returns (W, rate)."""
+                  sweeps: int = 1, per_column: bool = False, fail_weight=None):
+    """Coordinate search on the BP failure rate itself (or, with fail_weight,
+    on bp_cost): each block of weights -- one iteration and sweep direction,
+    or (per_column) one iteration, direction and stage column -- in turn is
+    scaled by the factor that lowers the objective on `llr` most, if any does.
+    Returns (W, objective)."""
     T = W.shape[0]
-    cur = bp_fail_rate(code, llr, W, T)
+    obj = (lambda w: bp_fail_rate(code, llr, w, T)) if fail_weight is None else \
+          (lambda w: bp_cost(code, llr, w, T, fail_weight))
+    cur = obj(W)
     blocks = [(t, d, s) for t in range(T) for d in range(2) for s in range(code.n)] if per_column else \
              [(t, d) for t in range(T) for d in range(2)]
     for _ in range(sweeps):
@@ -139,7 +149,7 @@ def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factor
             best_f, best_r = None, cur
             for f in factors:
                 W[blk] = base * f
-                r = bp_fail_rate(code, llr, W, T)
+                r = obj(W)
                 if r < best_r:
                     best_f, best_r = f, r
             W[blk] = base if best_f is None else base * best_f
