@@ -144,22 +144,48 @@ __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float m
 // pruned pseudo sort that Sec. II-A also describes): keys (metric bits, lane)
 // in the same strict order as candidate_rank, lanes without a candidate last;
 // after the network lane p holds the key of rank p, i.e. the candidate it takes.
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-    return (uint64_t)__shfl_xor((unsigned long long)v, m, 64);
+
+// value of lane (lane ^ J): data-parallel-primitive moves inside a row of 16
+// lanes for J <= 8 (J = 1, 2: one quad permute; J = 4: half-row mirror, then
+// quad reversal; J = 8: row mirror, then half-row mirror), a lane permute
+// through the LDS crossbar for J = 16, 32
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (J == 1) return dpp_mov<0xB1>(v);                   // quad_perm [1,0,3,2]
+    else if constexpr (J == 2) return dpp_mov<0x4E>(v);              // quad_perm [2,3,0,1]
+    else if constexpr (J == 4) return dpp_mov<0x1B>(dpp_mov<0x141>(v));  // half mirror, quad_perm [3,2,1,0]
+    else if constexpr (J == 8) return dpp_mov<0x141>(dpp_mov<0x140>(v));  // row mirror, half mirror
+    else return (uint32_t)__shfl_xor((int)v, J, 64);
+}
+
+template <int K, int J>
+__device__ __forceinline__ void bitonic_step(uint32_t& lo, uint32_t& hi, int lane) {
+    const uint32_t olo = lane_xor<J>(lo), ohi = lane_xor<J>(hi);
+    const uint64_t key = ((uint64_t)hi << 32) | lo;
+    const uint64_t o = ((uint64_t)ohi << 32) | olo;
+    const bool keep_min = ((lane & K) == 0) == ((lane & J) == 0);
+    const uint64_t r = keep_min ? (o < key ? o : key) : (o > key ? o : key);
+    lo = (uint32_t)r;
+    hi = (uint32_t)(r >> 32);
+    if constexpr (J > 1) bitonic_step<K, J / 2>(lo, hi, lane);
+}
+
+template <int K>
+__device__ __forceinline__ void bitonic_merge_all(uint32_t& lo, uint32_t& hi, int lane) {
+    bitonic_step<K, K / 2>(lo, hi, lane);
+    if constexpr (K < 64) bitonic_merge_all<K * 2>(lo, hi, lane);
 }
 
 __device__ __forceinline__ int bitonic_select(float met, int ncand, int lane) {
-    uint64_t key = lane < ncand ? (((uint64_t)__float_as_uint(met) << 32) | (uint64_t)lane) : ~0ull;
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t o = shfl_xor64(key, j);
-            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
-            key = keep_min ? (o < key ? o : key) : (o > key ? o : key);
-        }
-    }
-    return (int)(key & 63u);
+    uint32_t hi = lane < ncand ? __float_as_uint(met) : 0xFFFFFFFFu;
+    uint32_t lo = lane < ncand ? (uint32_t)lane : 0xFFFFFFFFu;
+    bitonic_merge_all<2>(lo, hi, lane);
+    return (int)(lo & 63u);
 }
 
 struct Layout {
