@@ -44,18 +44,27 @@ __device__ __forceinline__ uint64_t load_bits(const uint8_t* src) {
     return w;
 }
 
+// bits p of a 64-bit word with p & d == 0 (d a power of two)
+constexpr uint64_t low_half_mask(int d) {
+    uint64_t m = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((p & d) == 0) m |= 1ull << p;
+    return m;
+}
+
 // u G == x on the packed words of one frame; every checker lane gets the answer
 template <class G>
 __device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t* xb, int lane) {
     uint64_t u = load_bits<G>(ub + lane * G::CB);
     uint64_t x = load_bits<G>(xb + lane * G::CB);
-#pragma unroll
-    for (int d = 1; d < G::CB; d <<= 1) {
-        uint64_t m = 0;
-        for (int p = 0; p < 64; ++p)
-            if ((p & d) == 0) m |= 1ull << p;
-        u ^= (u >> d) & m;
-    }
+    // butterflies inside a word: distances 1, 2, .. CB/2 (masks fixed at compile time)
+    static_for<0, 6>([&](auto D) {
+        constexpr int d = 1 << decltype(D)::value;
+        if constexpr (d < G::CB) {
+            constexpr uint64_t m = low_half_mask(d);
+            u ^= (u >> d) & m;
+        }
+    });
 #pragma unroll
     for (int q = 1; q < G::TL; q <<= 1) {
         uint64_t o = (uint64_t)__shfl_xor((unsigned long long)u, q, 64);
@@ -119,6 +128,9 @@ template <class G, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false>
 __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io, int max_iter, int stop, float lmax,
                                          const float* __restrict__ W, BpShared<G>& sh, int t, int slot) {
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
+    // min-sum inference takes the sign-transfer form of g; training (SAVE)
+    // and the exact rule keep the direct form
+    constexpr bool FAST = RULE == 0 && !SAVE;
     float* tb = sh.tb;
     const int lane = (G::T < 64) ? t : (threadIdx.x & 63);
     uint8_t* ub = sh.ubytes + slot * N;
@@ -182,6 +194,29 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float r1 = (s == 0) ? prior[v] : Rm[s][v];
                     const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
                     const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
+                    if constexpr (FAST) {
+                        // both g terms share r1: its sign rides on the weight
+                        const float x = l2 + r2;
+                        if constexpr (WEIGHTED) {
+                            float wi, wj;
+                            if constexpr (WSTAGE) {
+                                wi = wj = Wit[0 * n + s];
+                            } else {
+                                const float* w = Wit + (size_t)(0 * n + s) * N + ib;
+                                wi = w[v << G::wbase(k)];
+                                wj = w[v2 << G::wbase(k)];
+                            }
+                            const float si = sign_to(wi, r1);
+                            const float sj = WSTAGE ? si : sign_to(wj, r1);
+                            Rm[s + 1][v] = clipf(si * clamp_mag(x, r1), lmax);
+                            Rm[s + 1][v2] = clipf(__fmaf_rn(sj, clamp_mag(l1, r1), r2), lmax);
+                        } else {
+                            const float si = sign_to(1.0f, r1);
+                            Rm[s + 1][v] = si * clamp_mag(x, r1);  // |g| <= |r1| <= lmax
+                            Rm[s + 1][v2] = clipf(__fmaf_rn(si, clamp_mag(l1, r1), r2), lmax);
+                        }
+                        continue;
+                    }
                     const float gi = g_rule<RULE>(r1, l2 + r2);
                     const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
@@ -230,6 +265,29 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                     const float r1 = (s == 0) ? prior[v] : Rm[s][v];
                     const float r2 = (s == 0) ? prior[v2] : Rm[s][v2];
                     const float l1 = Lm[s + 1][v], l2 = Lm[s + 1][v2];
+                    if constexpr (FAST) {
+                        // both g terms share l1
+                        const float x = l2 + r2;
+                        if constexpr (WEIGHTED) {
+                            float wi, wj;
+                            if constexpr (WSTAGE) {
+                                wi = wj = Wit[1 * n + s];
+                            } else {
+                                const float* w = Wit + (size_t)(1 * n + s) * N + ib;
+                                wi = w[v << G::wbase(k)];
+                                wj = w[v2 << G::wbase(k)];
+                            }
+                            const float si = sign_to(wi, l1);
+                            const float sj = WSTAGE ? si : sign_to(wj, l1);
+                            Lm[s][v] = clipf(si * clamp_mag(x, l1), lmax);
+                            Lm[s][v2] = clipf(__fmaf_rn(sj, clamp_mag(r1, l1), l2), lmax);
+                        } else {
+                            const float si = sign_to(1.0f, l1);
+                            Lm[s][v] = si * clamp_mag(x, l1);  // |g| <= |l1| <= lmax
+                            Lm[s][v2] = clipf(__fmaf_rn(si, clamp_mag(r1, l1), l2), lmax);
+                        }
+                        continue;
+                    }
                     const float gi = g_rule<RULE>(l1, l2 + r2);
                     const float gj = g_rule<RULE>(r1, l1);
                     if constexpr (WEIGHTED) {
@@ -326,8 +384,17 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
 
 // PERSIST: a grid smaller than the batch walks it (frame slots advance by the
 // grid size), so a capped grid leaves room on every CU for other kernels.
+// The N = 1024 inference kernel with one weight per stage column (128
+// threads per frame) fits 128 VGPRs without spilling inside its loop, which
+// lets four waves share a SIMD instead of three.
+template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, bool WSTAGE, bool PERSIST>
+constexpr int bp_waves_per_eu() {
+    return (NLOG == 10 && RLOG == 3 && WEIGHTED && WSTAGE && !SAVE && !PERSIST) ? 4 : 1;
+}
+
 template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false, bool PERSIST = false>
-__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_kernel(
+__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG))
+__attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, WSTAGE, PERSIST>()))) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
     const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
     int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, float* __restrict__ saved) {

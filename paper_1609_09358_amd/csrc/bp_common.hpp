@@ -33,6 +33,17 @@ __device__ __forceinline__ float g_ms(float a, float b) {
     return __uint_as_float(__float_as_uint(m) | s);
 }
 
+// Min-sum g in sign-transfer form: g(a, b) = sgn(a) * clamp(b, -|a|, |a|)
+// equals sgn(a) sgn(b) min(|a|, |b|) for every pair (a zero result may carry
+// the other sign, which no later value or decision depends on).  A PE's two g
+// terms share one operand, so its sign is moved once into the factor that
+// multiplies both: sign_to(w, a) = w with its sign flipped where a is negative
+// (one bit operation), clamp_mag(b, a) = the clamp (one med3).
+__device__ __forceinline__ float sign_to(float w, float a) {
+    return __uint_as_float(__float_as_uint(w) ^ (__float_as_uint(a) & 0x80000000u));
+}
+__device__ __forceinline__ float clamp_mag(float b, float a) { return __builtin_amdgcn_fmed3f(b, -fabsf(a), fabsf(a)); }
+
 // clip to [-m, m] (m > 0) in one instruction: the median of v, -m and m is
 // min(max(v, -m), m) for every non-NaN v, signed zeros included
 __device__ __forceinline__ float clipf(float v, float m) { return __builtin_amdgcn_fmed3f(v, -m, m); }
