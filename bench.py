@@ -241,11 +241,13 @@ def main():
                    reps) if nfail else 0.0
     iter_sum = int(bp_out["iters"].sum().item())
 
-    # algorithmic work of the weighted BP kernel: per PE and sweep 2 additions,
-    # 2 evaluations of g (magnitude minimum and sign product: 2 operations
-    # each), 2 weight multiplications and 2 clips = 10 operations; n*N/2 PEs
-    # and 2 sweeps per iteration
-    bp_ops = 10.0 * n * N * iter_sum
+    # algorithmic work of the weighted BP kernel, per PE and sweep: the input
+    # sum of the first output (1), the shared operand's sign moved onto the
+    # weight (1), the two min-sum terms as clamps of one input to the other's
+    # magnitude (2), the weight product of the first output (1), the weight
+    # product plus addition of the second (1, fused), 2 clips = 8 single-lane
+    # operations; n*N/2 PEs and 2 sweeps per iteration
+    bp_ops = 8.0 * n * N * iter_sum
     # algorithmic work of the SCL kernel: L * n * N / 2 f/g evaluations per frame
     scl_ops = float(L * n * N // 2) * nfail
     dominant = "bp_kernel" if bp_ms >= scl_ms else "scl_kernel"
