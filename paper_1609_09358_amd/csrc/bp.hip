@@ -132,7 +132,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     // and the exact rule keep the direct form
     constexpr bool FAST = RULE == 0 && !SAVE;
     float* tb = sh.tb;
-    const int lane = (G::T < 64) ? t : (threadIdx.x & 63);
+    const int lane = (G::T < 64) ? t : (lid_x() & 63);
     uint8_t* ub = sh.ubytes + slot * N;
     uint8_t* xb = sh.xbytes + slot * N;
 
@@ -401,13 +401,13 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
     using G = Geom<NLOG, RLOG>;
     constexpr int N = G::N;
     __shared__ BpShared<G> sh;
-    const int tid = threadIdx.x;
+    const int tid = lid_x();
     const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
     const int slot = (G::T < 64) ? (tid >> G::P) : 0;
-    const int64_t stride = PERSIST ? (int64_t)gridDim.x * G::FPW : 0;
-    for (int64_t f0 = (int64_t)blockIdx.x * G::FPW; f0 < B; f0 += stride) {
+    const int64_t stride = PERSIST ? num_groups_x() * G::FPW : 0;
+    for (int64_t f0 = gid_x() * G::FPW; f0 < B; f0 += stride) {
         const int64_t frame = f0 + slot;
-        if (PERSIST && G::T >= 64 && f0 != (int64_t)blockIdx.x * G::FPW) __syncthreads();  // staging reuse
+        if (PERSIST && G::T >= 64 && f0 != gid_x() * G::FPW) __syncthreads();  // staging reuse
         if (G::T < 64 && frame >= B) return;  // lone wavefront: no barriers to honour
         FrameIO io;
         io.llr = llr + frame * N;
@@ -433,14 +433,14 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
     int32_t* __restrict__ fail_count) {
     using G = Geom<NLOG, RLOG>;
     __shared__ BpShared<G> sh;
-    const int tid = threadIdx.x;
+    const int tid = lid_x();
     const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
     const int slot = (G::T < 64) ? (tid >> G::P) : 0;
     const int64_t cnt = *count;
     const float* llr = mio->llr;
     const int64_t* off = mio->off;
-    const int64_t stride = (int64_t)gridDim.x * G::FPW;
-    for (int64_t q0 = (int64_t)blockIdx.x * G::FPW; q0 < cnt; q0 += stride) {
+    const int64_t stride = num_groups_x() * G::FPW;
+    for (int64_t q0 = gid_x() * G::FPW; q0 < cnt; q0 += stride) {
         const int64_t q = q0 + slot;
         if (G::T >= 64) __syncthreads();  // the previous frame's staging is read
         if (q >= cnt) break;             // only when T < 64: this slot's wavefront lanes leave alone

@@ -16,44 +16,44 @@ __global__ __launch_bounds__(ENC_THREADS) void encode_kernel(CodeDev code, const
     extern __shared__ uint8_t su[];
     __shared__ uint32_t red[ENC_THREADS / 64];
     const int N = code.N, K = code.K, c = code.c;
-    const int64_t f = blockIdx.x;
+    const int64_t f = gid_x();
     const uint8_t* in = info + f * K;
-    for (int i = threadIdx.x; i < N; i += ENC_THREADS) su[i] = 0;
+    for (int i = lid_x(); i < N; i += ENC_THREADS) su[i] = 0;
     __syncthreads();
     uint32_t crc = 0;
-    for (int q = threadIdx.x; q < K; q += ENC_THREADS) {
+    for (int q = lid_x(); q < K; q += ENC_THREADS) {
         uint8_t b = in[q] & 1u;
         su[code.info_pos[q]] = b;
         if (b && c) crc ^= code.enc_crc[q];
     }
     if (c) {
         for (int m = 32; m >= 1; m >>= 1) crc ^= __shfl_xor(crc, m);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = crc;
+        if ((lid_x() & 63) == 0) red[lid_x() >> 6] = crc;
     }
     __syncthreads();
     if (c) {
         crc = 0;
         for (int w = 0; w < ENC_THREADS / 64; ++w) crc ^= red[w];
-        for (int j = threadIdx.x; j < c; j += ENC_THREADS) su[code.info_pos[K + j]] = (crc >> (c - 1 - j)) & 1u;
+        for (int j = lid_x(); j < c; j += ENC_THREADS) su[code.info_pos[K + j]] = (crc >> (c - 1 - j)) & 1u;
     }
     __syncthreads();
     if (u_out)
-        for (int i = threadIdx.x; i < N; i += ENC_THREADS) u_out[f * N + i] = su[i];
+        for (int i = lid_x(); i < N; i += ENC_THREADS) u_out[f * N + i] = su[i];
     __syncthreads();
     for (int d = 1; d < N; d <<= 1) {
-        for (int p = threadIdx.x; p < N / 2; p += ENC_THREADS) {
+        for (int p = lid_x(); p < N / 2; p += ENC_THREADS) {
             int i = (p / d) * 2 * d + (p % d);
             su[i] ^= su[i + d];
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < N; i += ENC_THREADS) x_out[f * N + i] = su[i];
+    for (int i = lid_x(); i < N; i += ENC_THREADS) x_out[f * N + i] = su[i];
 }
 
 __global__ void channel_kernel(const uint8_t* __restrict__ x, const float* __restrict__ z,
                                const float* __restrict__ sigma2, int64_t total, int32_t N,
                                float* __restrict__ llr) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t idx = gid_x() * wg_size_x() + lid_x();
     if (idx >= total) return;
     float s2 = sigma2[idx / N];
     float y = (x[idx] ? -1.0f : 1.0f) + sqrtf(s2) * z[idx];

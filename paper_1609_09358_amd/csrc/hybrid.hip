@@ -13,13 +13,13 @@ namespace polarhip {
 namespace {
 
 __global__ void clear_count_kernel(int32_t* count) {
-    if (threadIdx.x == 0) *count = 0;
+    if (lid_x() == 0) *count = 0;
 }
 
 // queue[] <- ids of frames with ok == 0; one atomic per wavefront
 __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ ok, int64_t B,
                                                       int32_t* __restrict__ queue, int32_t* __restrict__ count) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gid_x() * wg_size_x() + lid_x();
     const bool fail = f < B && ok[f] == 0;
     const uint64_t m = __ballot(fail);
     const int lane = __lane_id();
@@ -40,15 +40,15 @@ __global__ __launch_bounds__(256) void merge_kernel(CodeDev code, const uint8_t*
                                                     uint8_t* __restrict__ info_hat, uint8_t* __restrict__ used_scl,
                                                     unsigned long long* __restrict__ stats) {
     const int K = code.K, N = code.N;
-    const int64_t f0 = (int64_t)blockIdx.x * kMergeFrames;
+    const int64_t f0 = gid_x() * kMergeFrames;
     const int nf = (int)((B - f0) < kMergeFrames ? (B - f0) : kMergeFrames);
-    for (int it = threadIdx.x; it < nf * K; it += blockDim.x) {
+    for (int it = lid_x(); it < nf * K; it += wg_size_x()) {
         const int lf = it / K, q = it - lf * K;
         const int64_t f = f0 + lf;
         info_hat[f * K + q] = u_hat[f * N + code.info_pos[q]];
     }
-    if (threadIdx.x < 64) {
-        const int lf = threadIdx.x;
+    if (lid_x() < 64) {
+        const int lf = lid_x();
         unsigned long long s_bp = 0, s_scl = 0, s_it = 0, s_fail = 0, s_n = 0;
         if (lf < nf) {
             const int64_t f = f0 + lf;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hsa/hsa.h>
 
 #include <cstdint>
 #include <string>
@@ -11,6 +12,23 @@
 #include "../../include/polar.h"
 
 namespace polarhip {
+
+// Work-item and workgroup indices read from the registers the dispatch
+// initialises, grid and workgroup sizes from the dispatch packet.  HIP's
+// index variables go through device-library functions built with packed FP32
+// on; the inliner keeps them out of code built with it off, so every read
+// would be a call and the workgroup id a per-lane value.
+__device__ __forceinline__ int lid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int64_t gid_x() { return (int64_t)__builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ const hsa_kernel_dispatch_packet_t* dispatch_packet() {
+    return (const hsa_kernel_dispatch_packet_t*)__builtin_amdgcn_dispatch_ptr();
+}
+__device__ __forceinline__ int wg_size_x() { return (int)dispatch_packet()->workgroup_size_x; }
+__device__ __forceinline__ int64_t num_groups_x() {
+    const hsa_kernel_dispatch_packet_t* p = dispatch_packet();
+    const int64_t wg = p->workgroup_size_x;
+    return ((int64_t)p->grid_size_x + wg - 1) / wg;
+}
 
 // Device-side view of a code, passed to kernels by value.
 struct CodeDev {

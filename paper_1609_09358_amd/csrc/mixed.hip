@@ -35,17 +35,17 @@ struct MixedArgs {
 };
 
 __global__ void set_args_kernel(MixedArgs* d, MixedArgs v) {
-    if (threadIdx.x == 0) *d = v;
+    if (lid_x() == 0) *d = v;
 }
 
 __global__ void clear_kernel(int32_t* c, int n) {
-    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+    if ((int)lid_x() < n) c[lid_x()] = 0;
 }
 
 // ids of code c: lists[c * cap + ...], cnt[c] of them
 __global__ __launch_bounds__(256) void bucket_kernel(const MixedArgs* __restrict__ a, int n_codes, int64_t cap,
                                                      int32_t* __restrict__ lists, int32_t* __restrict__ cnt) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = gid_x() * wg_size_x() + lid_x();
     if (f >= a->B || f >= cap) return;
     const int c = a->code_of_frame[f];
     if (c < 0 || c >= n_codes) return;
@@ -58,15 +58,15 @@ __global__ __launch_bounds__(64) void mixed_merge_kernel(const MixedArgs* __rest
                                                          const uint8_t* __restrict__ ok,
                                                          const int32_t* __restrict__ iters,
                                                          const uint8_t* __restrict__ scl_ok) {
-    const int64_t f = blockIdx.x;
+    const int64_t f = gid_x();
     if (f >= a->B) return;
     const int c = a->code_of_frame[f];
     if (c < 0 || c >= n_codes) return;
     const CodeDev& cd = codes[c];
     const uint8_t* uf = u + f * u_stride;
     uint8_t* dst = a->info_hat + a->out_off[f];
-    for (int q = threadIdx.x; q < cd.K; q += 64) dst[q] = uf[cd.info_pos[q]];
-    if (threadIdx.x == 0) {
+    for (int q = lid_x(); q < cd.K; q += 64) dst[q] = uf[cd.info_pos[q]];
+    if (lid_x() == 0) {
         const bool good = ok[f] != 0;
         if (a->used_scl) a->used_scl[f] = good ? 0 : 1;
         if (a->stats) {

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                                                  Layout lay, const MixedIo* __restrict__ mio) {
     constexpr int BS = 1 << BL;  // bits per block
     extern __shared__ __attribute__((aligned(16))) unsigned char sm[];
-    const int lane = threadIdx.x;
+    const int lane = lid_x();
     const int n = code.n, N = code.N;
     const int gl = lay.gl, SL = lay.sl, PW = lay.pw;
 
@@ -233,14 +233,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     uint8_t* tbk = sm + lay.tboff;                                // [k][L] unless tg
     uint8_t* dec = reinterpret_cast<uint8_t*>(slam);              // [N], reuses the LLR area at the end
 
-    unsigned char* gbase = glob_all ? glob_all + (size_t)blockIdx.x * (size_t)lay.gbytes : nullptr;
+    unsigned char* gbase = glob_all ? glob_all + (size_t)gid_x() * (size_t)lay.gbytes : nullptr;
     float* glam = reinterpret_cast<float*>(gbase);            // [L][N], levels >= gl
     uint8_t* tbg = lay.tg ? gbase + lay.toff : nullptr;       // [k][L] when tg
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
     const float* const llr_base = mio ? mio->llr : llr;
     const int64_t* const row_off = mio ? mio->off : nullptr;
-    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
+    for (int64_t q = gid_x(); q < count; q += num_groups_x()) {
         const int64_t f = frame_ids ? (int64_t)frame_ids[q] : q;
         // rows of frame f: LLRs at row_off[f] (ragged batch) or f * N; u_hat at
         // f * u_stride (ragged batch) or f * N

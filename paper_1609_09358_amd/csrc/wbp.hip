@@ -40,10 +40,10 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void wbp_bwd_kernel(
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
     __shared__ float tb[G::TAB.words];
 
-    const int tid = threadIdx.x;
+    const int tid = lid_x();
     const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
     const int slot = (G::T < 64) ? (tid >> G::P) : 0;
-    const int64_t frame = (int64_t)blockIdx.x * G::FPW + slot;
+    const int64_t frame = gid_x() * G::FPW + slot;
     if (G::T < 64 && frame >= B) return;
 
     int bfrom[G::NB > 0 ? G::NB : 1], bto[G::NB > 0 ? G::NB : 1];
@@ -243,7 +243,7 @@ namespace {
 // dW[q] = sum over frames, in frame order, of the per-frame gradients
 __global__ __launch_bounds__(256) void wbp_reduce_kernel(const float* __restrict__ part, int64_t B, int64_t P,
                                                          float* __restrict__ dW) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = gid_x() * wg_size_x() + lid_x();
     if (q >= P) return;
     double acc = 0.0;
     for (int64_t f = 0; f < B; ++f) acc += (double)part[f * P + q];
@@ -256,10 +256,10 @@ __global__ __launch_bounds__(256) void wbp_bce_kernel(CodeDev code, const float*
                                                       const uint8_t* __restrict__ u, int64_t B, double scale,
                                                       float* __restrict__ loss, float* __restrict__ dlam) {
     __shared__ double red[256 / 64];
-    const int64_t f = blockIdx.x;
+    const int64_t f = gid_x();
     const int N = code.N;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    for (int i = lid_x(); i < N; i += wg_size_x()) {
         const bool fr = (code.frozen_bits[i >> 5] >> (i & 31)) & 1u;
         float d = 0.0f;
         if (!fr) {
@@ -273,11 +273,11 @@ __global__ __launch_bounds__(256) void wbp_bce_kernel(CodeDev code, const float*
     }
     if (loss) {
         for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        if ((lid_x() & 63) == 0) red[lid_x() >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (lid_x() == 0) {
             double tot = 0.0;
-            for (int w = 0; w < (int)(blockDim.x / 64); ++w) tot += red[w];
+            for (int w = 0; w < (int)(wg_size_x() / 64); ++w) tot += red[w];
             loss[f] = (float)(tot * scale);
         }
     }
@@ -290,13 +290,13 @@ __global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const 
                                                             const uint8_t* __restrict__ u, int T, double scale,
                                                             float* __restrict__ loss, float* __restrict__ dlam) {
     __shared__ double red[256 / 64];
-    const int64_t f = blockIdx.x;
+    const int64_t f = gid_x();
     const int N = code.N, n = code.n;
     double acc = 0.0;
     for (int t = 0; t < T; ++t) {
         const float* lrow = saved + (((size_t)f * T + t) * 2 * n + n) * N;
         float* drow = dlam + ((size_t)f * T + t) * N;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        for (int i = lid_x(); i < N; i += wg_size_x()) {
             const bool fr = (code.frozen_bits[i >> 5] >> (i & 31)) & 1u;
             float d = 0.0f;
             if (!fr) {
@@ -312,11 +312,11 @@ __global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const 
     }
     if (loss) {
         for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        if ((lid_x() & 63) == 0) red[lid_x() >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (lid_x() == 0) {
             double tot = 0.0;
-            for (int w = 0; w < (int)(blockDim.x / 64); ++w) tot += red[w];
+            for (int w = 0; w < (int)(wg_size_x() / 64); ++w) tot += red[w];
             loss[f] = (float)(tot * scale);
         }
     }
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const 
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t count,
                                                    float lr, float b1, float b2, float eps, float c1, float c2) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = gid_x() * wg_size_x() + lid_x();
     if (q >= count) return;
     const float gq = g[q];
     const float mq = b1 * m[q] + (1.0f - b1) * gq;
