@@ -145,45 +145,61 @@ __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float m
 // in the same strict order as candidate_rank, lanes without a candidate last;
 // after the network lane p holds the key of rank p, i.e. the candidate it takes.
 
-// value of lane (lane ^ J), all in VALU: data-parallel-primitive moves inside
-// a row of 16 lanes for J <= 8 (J = 1, 2: one quad permute; J = 4: half-row
-// mirror, then quad reversal; J = 8: row mirror, then half-row mirror); for
-// J = 16, 32 the gfx950 row swaps, which exchange the upper rows of their
-// first operand with the lower rows of the second -- with the value in both,
-// the second result holds the partner for lanes whose bit J is clear, the
-// first for the others
+// The keys of lane and of lane ^ J, all in VALU: data-parallel-primitive
+// moves inside a row of 16 lanes for J <= 8 (J = 1, 2: one quad permute;
+// J = 4: half-row mirror, then quad reversal; J = 8: row mirror, then
+// half-row mirror), giving (own, partner); for J = 16, 32 the gfx950 row
+// swaps, which exchange the upper rows of their first operand with the lower
+// rows of the second -- with the key in both, every lane ends up holding its
+// own key and its partner's, in an order that depends on the lane, which a
+// compare-exchange does not need to know.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
 
 template <int J>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
     if constexpr (J == 1) {
         return dpp_mov<0xB1>(v);  // quad_perm [1,0,3,2]
     } else if constexpr (J == 2) {
         return dpp_mov<0x4E>(v);  // quad_perm [2,3,0,1]
     } else if constexpr (J == 4) {
         return dpp_mov<0x1B>(dpp_mov<0x141>(v));  // half mirror, quad_perm [3,2,1,0]
-    } else if constexpr (J == 8) {
-        return dpp_mov<0x141>(dpp_mov<0x140>(v));  // row mirror, half mirror
-    } else if constexpr (J == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (lane & 16) ? r[0] : r[1];
     } else {
-        static_assert(J == 32, "distance");
-        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-        return (lane & 32) ? r[0] : r[1];
+        static_assert(J == 8, "distance");
+        return dpp_mov<0x141>(dpp_mov<0x140>(v));  // row mirror, half mirror
     }
 }
 
+template <int J>
+__device__ __forceinline__ void key_pair(uint32_t lo, uint32_t hi, uint64_t& a, uint64_t& b) {
+    if constexpr (J <= 8) {
+        a = ((uint64_t)hi << 32) | lo;
+        b = ((uint64_t)lane_xor<J>(hi) << 32) | lane_xor<J>(lo);
+    } else if constexpr (J == 16) {
+        const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a = ((uint64_t)rh[0] << 32) | rl[0];
+        b = ((uint64_t)rh[1] << 32) | rl[1];
+    } else {
+        static_assert(J == 32, "distance");
+        const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a = ((uint64_t)rh[0] << 32) | rl[0];
+        b = ((uint64_t)rh[1] << 32) | rl[1];
+    }
+}
+
+// compare-exchange at distance J inside sorted runs of 2K: the lane keeps the
+// smaller key of {a, b} or the larger, by its position (keys are distinct
+// except the padding ones, which are equal, so taking b on a tie is harmless)
 template <int K, int J>
 __device__ __forceinline__ void bitonic_step(uint32_t& lo, uint32_t& hi, int lane) {
-    const uint32_t olo = lane_xor<J>(lo, lane), ohi = lane_xor<J>(hi, lane);
-    const uint64_t key = ((uint64_t)hi << 32) | lo;
-    const uint64_t o = ((uint64_t)ohi << 32) | olo;
-    const bool keep_min = ((lane & K) == 0) == ((lane & J) == 0);
-    const uint64_t r = keep_min ? (o < key ? o : key) : (o > key ? o : key);
+    uint64_t a, b;
+    key_pair<J>(lo, hi, a, b);
+    const bool keep_max = ((lane & K) == 0) != ((lane & J) == 0);
+    const uint64_t r = ((b < a) != keep_max) ? b : a;
     lo = (uint32_t)r;
     hi = (uint32_t)(r >> 32);
     if constexpr (J > 1) bitonic_step<K, J / 2>(lo, hi, lane);
