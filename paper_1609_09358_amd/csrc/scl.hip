@@ -42,10 +42,13 @@
 namespace polarhip {
 namespace scl {
 
-__device__ __forceinline__ float g_ms(float a, float b) {
-    float m = fminf(fabsf(a), fabsf(b));
-    uint32_t s = (__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u;
-    return __uint_as_float(__float_as_uint(m) | s);
+// Min-sum f (the check-node rule with min-sum, Sec. II-A): sgn(a) sgn(b)
+// min(|a|, |b|), as b clamped to [-|a|, |a|] with a's sign applied -- one med3
+// and one bit operation; a zero result may carry the other sign, which no
+// decision, penalty or metric depends on.
+__device__ __forceinline__ float f_ms(float a, float b) {
+    const float m = __builtin_amdgcn_fmed3f(b, -fabsf(a), fabsf(a));
+    return __uint_as_float(__float_as_uint(m) ^ (__float_as_uint(a) & 0x80000000u));
 }
 
 __device__ __forceinline__ void wave_mem_order() {
@@ -286,59 +289,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                 const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
                 for (int d = top; d >= BL; --d) {
                     const int sz = 1 << d;
-                    const int items = act << d;
                     const int myp = get_byte(ptrL, d + 1);
                     const int mypp = get_byte(ptrP, d);
-                    // four items per lane per pass: all loads issued before any use
-                    for (int it0 = lane; it0 < items; it0 += 256) {
-                        float a[4], b[4];
+                    // units of four consecutive items of one slot (a level has at
+                    // least 32 per slot), two units per lane per pass with all loads
+                    // issued before any use; every lane runs every pass, so the lane
+                    // shuffles read active lanes only (units past the end redo unit
+                    // 0 and store nothing)
+                    const int units = act << (d - 2);
+                    const bool psum = d == top && j != 0;
+                    for (int u0 = 0; u0 < units; u0 += 128) {
+                        float a[2][4], b[2][4];
+                        int slot[2], e[2];
+                        bool live[2];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int it = it0 + 64 * u;
-                            const int slot = (it < items ? it : it0) >> d;
-                            const int e = it & (sz - 1);
+                        for (int h = 0; h < 2; ++h) {
+                            const int uu = u0 + 64 * h + lane;
+                            live[h] = uu < units;
+                            const int it = (live[h] ? uu : 0) << 2;
+                            slot[h] = it >> d;
+                            e[h] = it & (sz - 1);
                             if (d + 1 == n) {
-                                a[u] = chan[e];
-                                b[u] = chan[e + sz];
-                            } else {
-                                const int src = (d == top) ? __shfl(myp, slot, 64) : slot;
-                                if (it < items) {
-                                    if (d + 1 < gl) {
-                                        const float* p = slam + src * SL + ((2 << d) - BS);
-                                        a[u] = p[e];
-                                        b[u] = p[e + sz];
-                                    } else {
-                                        const float* p = glam + (size_t)src * N + (2 << d);
-                                        a[u] = p[e];
-                                        b[u] = p[e + sz];
-                                    }
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) {
+                                    a[h][k] = chan[e[h] + k];
+                                    b[h][k] = chan[e[h] + sz + k];
                                 }
+                            } else {
+                                const int src = (d == top) ? __shfl(myp, slot[h], 64) : slot[h];
+                                const float* p = (d + 1 < gl) ? slam + src * SL + ((2 << d) - BS) + e[h]
+                                                              : glam + (size_t)src * N + (2 << d) + e[h];
+                                const float4 ta = *reinterpret_cast<const float4*>(p);
+                                const float4 tb = *reinterpret_cast<const float4*>(p + sz);
+                                a[h][0] = ta.x; a[h][1] = ta.y; a[h][2] = ta.z; a[h][3] = ta.w;
+                                b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
                             }
                         }
-                        uint32_t w[4];
-                        if (d == top && j != 0) {
+                        uint32_t w[2] = {0u, 0u};
+                        if (psum) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int it = it0 + 64 * u;
-                                const int slot = (it < items ? it : it0) >> d;
-                                const int e = it & (sz - 1);
-                                const int pss = __shfl(mypp, slot, 64);
-                                w[u] = it < items ? psw[pss * PW + ps_off(d) + (e >> 5)] : 0u;
+                            for (int h = 0; h < 2; ++h) {
+                                const int pss = __shfl(mypp, slot[h], 64);
+                                w[h] = psw[pss * PW + ps_off(d) + (e[h] >> 5)] >> (e[h] & 31);
                             }
                         }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int it = it0 + 64 * u;
-                            if (it >= items) continue;
-                            const int slot = it >> d;
-                            const int e = it & (sz - 1);
-                            float val;
-                            if (d == top && j != 0)
-                                val = ((w[u] >> (e & 31)) & 1u) ? b[u] - a[u] : b[u] + a[u];
-                            else
-                                val = g_ms(a[u], b[u]);
-                            if (d < gl) slam[slot * SL + sz - BS + e] = val;
-                            else glam[(size_t)slot * N + sz + e] = val;
+                        for (int h = 0; h < 2; ++h) {
+                            float v[4];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                v[k] = psum ? (((w[h] >> k) & 1u) ? b[h][k] - a[h][k] : b[h][k] + a[h][k])
+                                            : f_ms(a[h][k], b[h][k]);
+                            if (live[h]) {
+                                float* q = (d < gl) ? slam + slot[h] * SL + sz - BS + e[h]
+                                                    : glam + (size_t)slot[h] * N + sz + e[h];
+                                *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
+                            }
                         }
                     }
                     if (d < gl) wave_mem_order(); else wg_mem_order();
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                             if (r != 0 && d == top)
                                 lv[(1 << d) + e] = ((ps[d] >> e) & 1u) ? b - a : b + a;
                             else
-                                lv[(1 << d) + e] = g_ms(a, b);
+                                lv[(1 << d) + e] = f_ms(a, b);
                         }
                     }
                 }
