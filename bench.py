@@ -245,9 +245,12 @@ def main():
     # sum of the first output (1), the shared operand's sign moved onto the
     # weight (1), the two min-sum terms as clamps of one input to the other's
     # magnitude (2), the weight product of the first output (1), the weight
-    # product plus addition of the second (1, fused), 2 clips = 8 single-lane
-    # operations; n*N/2 PEs and 2 sweeps per iteration
-    bp_ops = 8.0 * n * N * iter_sum
+    # product plus addition of the second (1, fused), the clip of the second
+    # (1) and that of the first (1) unless every weight is within [-1, 1],
+    # where it cannot act = 7 or 8 single-lane operations; n*N/2 PEs and 2
+    # sweeps per iteration
+    w_unit = float(W.abs().max()) <= 1.0
+    bp_ops = (7.0 if w_unit else 8.0) * n * N * iter_sum
     # algorithmic work of the SCL kernel: L * n * N / 2 f/g evaluations per frame
     scl_ops = float(L * n * N // 2) * nfail
     dominant = "bp_kernel" if bp_ms >= scl_ms else "scl_kernel"
@@ -281,6 +284,8 @@ def main():
         "mean_bp_iterations": float(st[3]) / B,
         "mean_bp_iterations_plain": float(st_p[3]) / B,
         "kernel_ms": {"bp_kernel": round(bp_ms, 4), "scl_kernel": round(scl_ms, 4)},
+        "bp_ops_per_pe_sweep": 7 if w_unit else 8,
+        "weights_max_abs": round(float(W.abs().max()), 4),
         "scl_frames": nfail,
         "weights": {"layout": "per stage column [T][2][n]", "alpha": alpha, "val_fail_scale": rate0,
                     "val_fail_blocks": rate1, "val_fail_columns": rate_ref, "fit_seconds": round(fit_s, 1)},

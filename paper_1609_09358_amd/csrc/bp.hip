@@ -124,7 +124,10 @@ struct FrameIO {
 
 // Decode one frame: thread t of the frame's T threads, frame slot `slot` of
 // its wavefront (T < 64) or workgroup.  Returns the verdict (for queues).
-template <class G, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false>
+// NOCLIP (per-stage weights, every weight within [-1, 1]): the first output
+// of a PE is w g with |w g| <= |g| <= lmax, so its clip would return its input
+// and is left out.
+template <class G, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAGE = false, bool NOCLIP = false>
 __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io, int max_iter, int stop, float lmax,
                                          const float* __restrict__ W, BpShared<G>& sh, int t, int slot) {
     constexpr int n = G::n, N = G::N, V = G::V, KL = G::NWIN - 1;
@@ -208,7 +211,8 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                             }
                             const float si = sign_to(wi, r1);
                             const float sj = WSTAGE ? si : sign_to(wj, r1);
-                            Rm[s + 1][v] = clipf(si * clamp_mag(x, r1), lmax);
+                            const float yi = si * clamp_mag(x, r1);
+                            Rm[s + 1][v] = NOCLIP ? yi : clipf(yi, lmax);
                             Rm[s + 1][v2] = clipf(__fmaf_rn(sj, clamp_mag(l1, r1), r2), lmax);
                         } else {
                             const float si = sign_to(1.0f, r1);
@@ -279,7 +283,8 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                             }
                             const float si = sign_to(wi, l1);
                             const float sj = WSTAGE ? si : sign_to(wj, l1);
-                            Lm[s][v] = clipf(si * clamp_mag(x, l1), lmax);
+                            const float yi = si * clamp_mag(x, l1);
+                            Lm[s][v] = NOCLIP ? yi : clipf(yi, lmax);
                             Lm[s][v2] = clipf(__fmaf_rn(sj, clamp_mag(r1, l1), l2), lmax);
                         } else {
                             const float si = sign_to(1.0f, l1);
@@ -405,6 +410,14 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
     const int t = (G::T < 64) ? (tid & (G::T - 1)) : tid;
     const int slot = (G::T < 64) ? (tid >> G::P) : 0;
     const int64_t stride = PERSIST ? num_groups_x() * G::FPW : 0;
+    // per-stage weights all within [-1, 1]: the clip-free form applies (every
+    // wavefront reads the max_iter * 2n weights, which sit in the caches)
+    bool unit = false;
+    if constexpr (WEIGHTED && WSTAGE && RULE == 0 && !SAVE) {
+        float m = 0.0f;
+        for (int i = tid & 63; i < max_iter * 2 * G::n; i += 64) m = fmaxf(m, fabsf(W[i]));
+        unit = wave_max(m) <= 1.0f;
+    }
     for (int64_t f0 = gid_x() * G::FPW; f0 < B; f0 += stride) {
         const int64_t frame = f0 + slot;
         if (PERSIST && G::T >= 64 && f0 != gid_x() * G::FPW) __syncthreads();  // staging reuse
@@ -416,7 +429,12 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
         io.iters = iters_out ? iters_out + frame : nullptr;
         io.ok = ok_out ? ok_out + frame : nullptr;
         io.saved = SAVE ? saved + (size_t)frame * max_iter * 2 * G::n * N : nullptr;
-        bp_frame<G, WEIGHTED, SAVE, RULE, WSTAGE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        if constexpr (WEIGHTED && WSTAGE && RULE == 0 && !SAVE) {
+            if (unit) bp_frame<G, true, false, 0, true, true>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+            else bp_frame<G, true, false, 0, true, false>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        } else {
+            bp_frame<G, WEIGHTED, SAVE, RULE, WSTAGE>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        }
         if (!PERSIST) break;
     }
 }

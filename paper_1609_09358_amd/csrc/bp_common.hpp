@@ -44,6 +44,13 @@ __device__ __forceinline__ float sign_to(float w, float a) {
 }
 __device__ __forceinline__ float clamp_mag(float b, float a) { return __builtin_amdgcn_fmed3f(b, -fabsf(a), fabsf(a)); }
 
+// maximum over the wavefront, in every lane
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int q = 1; q < 64; q <<= 1) v = fmaxf(v, __shfl_xor(v, q, 64));
+    return v;
+}
+
 // clip to [-m, m] (m > 0) in one instruction: the median of v, -m and m is
 // min(max(v, -m), m) for every non-NaN v, signed zeros included
 __device__ __forceinline__ float clipf(float v, float m) { return __builtin_amdgcn_fmed3f(v, -m, m); }

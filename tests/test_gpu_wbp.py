@@ -183,12 +183,20 @@ def test_multi_loss_end_to_end_vs_oracle(T):
 
 @pytest.mark.parametrize("N,K,c,T", [(64, 32, 0, 6), (1024, 512, 24, 12)])
 @pytest.mark.parametrize("variant", [2, 3])
-def test_per_stage_weights_equal_expanded_per_node_weights(N, K, c, T, variant):
+@pytest.mark.parametrize("lo,hi", [(0.8, 1.1), (0.5, 1.0), (-1.0, 1.0)])
+def test_per_stage_weights_equal_expanded_per_node_weights(N, K, c, T, variant, lo, hi):
     """One weight per stage column (scalar loads) decodes exactly like the
-    same weights repeated over the column's nodes, with early stopping."""
+    same weights repeated over the column's nodes, with early stopping.  With
+    every weight within [-1, 1] (the ranges ending at 1.0, which also hold
+    weights of exactly 1 and -1 and, in the last, negative ones) the
+    per-stage kernel leaves out the clips that cannot act; above 1 it keeps
+    them."""
     n = N.bit_length() - 1
     code, u, llr = frames(N, K, c, 2.0, 40, seed=N + T + variant)
-    Ws = torch.from_numpy(np.random.default_rng(T).uniform(0.8, 1.1, (T, 2, n)).astype(np.float32)).cuda()
+    w = np.random.default_rng(T).uniform(lo, hi, (T, 2, n)).astype(np.float32)
+    if hi == 1.0:
+        w[0, 0, 0], w[1, 1, n - 1] = 1.0, -1.0 if lo < 0 else 1.0
+    Ws = torch.from_numpy(w).cuda()
     Wn = Ws[..., None].expand(T, 2, n, N).contiguous()
     a = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=1, weights=Ws, variant=variant, soft=True)
     b = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=1, weights=Wn, variant=variant, soft=True)
