@@ -44,6 +44,23 @@ __device__ __forceinline__ uint64_t load_bits(const uint8_t* src) {
     return w;
 }
 
+// Packed u decisions (V = 8 and a frame of at least one wavefront): bit j of
+// the frame's bit array is node j.  Checker lane l's CB consecutive bits, read
+// in one access.
+template <class G>
+__device__ __forceinline__ uint64_t read_bits(const uint8_t* bits, int lane) {
+    if constexpr (G::CB == 8) return bits[lane];
+    else if constexpr (G::CB == 16) return reinterpret_cast<const uint16_t*>(bits)[lane];
+    else if constexpr (G::CB == 32) return reinterpret_cast<const uint32_t*>(bits)[lane];
+    else return reinterpret_cast<const uint64_t*>(bits)[lane];
+}
+
+template <class G, bool PACKED>
+__device__ __forceinline__ uint64_t lane_bits(const uint8_t* src, int lane) {
+    if constexpr (PACKED) return read_bits<G>(src, lane);
+    else return load_bits<G>(src + lane * G::CB);
+}
+
 // bits p of a 64-bit word with p & d == 0 (d a power of two)
 constexpr uint64_t low_half_mask(int d) {
     uint64_t m = 0;
@@ -53,9 +70,9 @@ constexpr uint64_t low_half_mask(int d) {
 }
 
 // u G == x on the packed words of one frame; every checker lane gets the answer
-template <class G>
+template <class G, bool PACKED>
 __device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t* xb, int lane) {
-    uint64_t u = load_bits<G>(ub + lane * G::CB);
+    uint64_t u = lane_bits<G, PACKED>(ub, lane);
     uint64_t x = load_bits<G>(xb + lane * G::CB);
     // butterflies inside a word: distances 1, 2, .. CB/2 (masks fixed at compile time)
     static_for<0, 6>([&](auto D) {
@@ -78,10 +95,10 @@ __device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t*
     return bad == 0;
 }
 
-template <class G>
+template <class G, bool PACKED>
 __device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub, int lane) {
     if (code.c == 0) return true;
-    uint64_t u = load_bits<G>(ub + lane * G::CB);
+    uint64_t u = lane_bits<G, PACKED>(ub, lane);
     uint32_t s = 0;
     const uint32_t* tab = code.syn_nib + (size_t)(lane * G::CB / 4) * 16;
     if constexpr (G::CB >= 4) {
@@ -134,6 +151,9 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     // min-sum inference takes the sign-transfer form of g; training (SAVE)
     // and the exact rule keep the direct form
     constexpr bool FAST = RULE == 0 && !SAVE;
+    // u decisions stored as bits, one byte per thread of window 0 (its eight
+    // consecutive nodes), instead of one byte each; x decisions stay bytes
+    constexpr bool BITPACK = G::V == 8 && G::T >= 64;
     float* tb = sh.tb;
     const int lane = (G::T < 64) ? t : (lid_x() & 63);
     uint8_t* ub = sh.ubytes + slot * N;
@@ -322,7 +342,17 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             }
         });
         // ---------------- decisions in window 0 (register bits are the low bits)
-        {
+        if constexpr (BITPACK) {
+            // nodes 8t .. 8t + 7: byte t of the bit array
+            uint32_t bits = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                L0[v] = Lm[0][v];
+                const float lu = Lm[0][v] + prior[v];
+                bits |= (((fmask >> v) & 1u) == 0 && lu < 0.0f) ? (1u << v) : 0u;
+            }
+            ub[t] = (uint8_t)bits;
+        } else {
             uint64_t pack = 0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -347,19 +377,19 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
         const bool last = it >= max_iter;
         if (stop == 1) {
             frame_sync<G>();
-            gok = reencode_check<G>(ub, xb, lane);
+            gok = reencode_check<G, BITPACK>(ub, xb, lane);
             if (gok || last) {
-                cok = crc_check<G>(code, ub, lane);
+                cok = crc_check<G, BITPACK>(code, ub, lane);
                 break;
             }
         } else if (stop == 2) {
             frame_sync<G>();
-            cok = crc_check<G>(code, ub, lane);
+            cok = crc_check<G, BITPACK>(code, ub, lane);
             if (cok || last) break;
         } else if (last) {
             frame_sync<G>();
-            gok = reencode_check<G>(ub, xb, lane);
-            cok = crc_check<G>(code, ub, lane);
+            gok = reencode_check<G, BITPACK>(ub, xb, lane);
+            cok = crc_check<G, BITPACK>(code, ub, lane);
             break;
         }
     }
@@ -370,9 +400,17 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
         const int ib = idx_base<G, 0>(t);
         if (io.u_hat) {
             uint8_t* uo = io.u_hat + ib;
-            const uint8_t* src = ub + ib;
+            if constexpr (BITPACK) {
+                const uint32_t ubits = ub[t];  // the last iteration's decisions
+                uint64_t bytes = 0;
 #pragma unroll
-            for (int v = 0; v < V; ++v) uo[v] = src[v];
+                for (int v = 0; v < V; ++v) bytes |= (uint64_t)((ubits >> v) & 1u) << (8 * v);
+                *reinterpret_cast<uint64_t*>(uo) = bytes;
+            } else {
+                const uint8_t* src = ub + ib;
+#pragma unroll
+                for (int v = 0; v < V; ++v) uo[v] = src[v];
+            }
         }
         if (io.llr_u) {
             float* lo = io.llr_u + ib;
