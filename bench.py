@@ -21,7 +21,8 @@ column), shared by the column's nodes.  Its weights are fitted before timing
 (untimed, seeded, on validation frames drawn apart from the timed ones): the
 normalized min-sum scale with the fewest BP failures, then a coordinate search
 on the failure rate over (iteration, direction) blocks and then over single
-(iteration, direction, column) weights.  The plain hybrid
+(iteration, direction, column) weights, each weight kept within [0, 1] (a
+learned weight never amplifies a message).  The plain hybrid
 (unweighted BP, at most 200 iterations, then the same CA-SCL) decodes the same
 frames for comparison; the throughput counts only if the learned decoder's
 frame error rate does not exceed the upper 95% Clopper-Pearson bound of the
@@ -123,8 +124,8 @@ def main():
     val_gen = TW.Trainer(code, 1, 16, seed=9358)
     _, _, val_llr = val_gen.frames(1 << 17, ebn0=args.ebn0)
     W0, alpha, rate0 = TW.fit_scale(code, val_llr, T, per_stage=True)
-    W1, rate1 = TW.refine_blocks(code, val_llr, W0.clone())
-    W, rate_ref = TW.refine_blocks(code, val_llr, W1.clone(), per_column=True)
+    W1, rate1 = TW.refine_blocks(code, val_llr, W0.clone(), wmax=1.0)
+    W, rate_ref = TW.refine_blocks(code, val_llr, W1.clone(), per_column=True, wmax=1.0)
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t_fit
     log(stage="weights", alpha=alpha, val_fail_scale=rate0, val_fail_blocks=rate1, val_fail_columns=rate_ref,

@@ -131,12 +131,14 @@ def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stag
 
 
 def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factors=(0.96, 0.98, 1.02, 1.04),
-                  sweeps: int = 1, per_column: bool = False, fail_weight=None):
+                  sweeps: int = 1, per_column: bool = False, fail_weight=None, wmax=None):
     """Coordinate search on the BP failure rate itself (or, with fail_weight,
     on bp_cost): each block of weights -- one iteration and sweep direction,
     or (per_column) one iteration, direction and stage column -- in turn is
     scaled by the factor that lowers the objective on `llr` most, if any does.
-    Returns (W, objective)."""
+    wmax: scaled weights are kept within [-wmax, wmax] (wmax = 1: the decoder
+    never amplifies a check-node message, and the per-stage kernel then skips
+    the clips that cannot act).  Returns (W, objective)."""
     T = W.shape[0]
     obj = (lambda w: bp_fail_rate(code, llr, w, T)) if fail_weight is None else \
           (lambda w: bp_cost(code, llr, w, T, fail_weight))
@@ -148,11 +150,11 @@ def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factor
             base = W[blk].clone()
             best_f, best_r = None, cur
             for f in factors:
-                W[blk] = base * f
+                W[blk] = base * f if wmax is None else (base * f).clamp(-wmax, wmax)
                 r = obj(W)
                 if r < best_r:
                     best_f, best_r = f, r
-            W[blk] = base if best_f is None else base * best_f
+            W[blk] = base if best_f is None else (base * best_f if wmax is None else (base * best_f).clamp(-wmax, wmax))
             cur = best_r
     return W, cur
 
