@@ -242,17 +242,21 @@ int32_t polar_get_pipeline_bp_occupancy(void);
  * hybrid decoder of Sec. III applied frame by frame with each frame's code.
  * A plan holds up to 16 codes (all of the current device), the BP parameters
  * (unweighted; params->variant is replaced by variants[c] when variants is
- * not NULL, 0 = default layout), the list size and its own device workspace
+ * not NULL, 0 = default layout; codes of one block length share the BP
+ * kernel of the first of them, and so its layout), the list size and its own
+ * device workspace
  * for up to max_frames frames per call; creating it allocates, calls do not.
  * A call decodes B frames in any order: frame f uses code code_of_frame[f]
  * (frames with an id outside [0, n_codes) are skipped), its N LLRs start at
  * element llr_off[f] of llr and its K information bits are written from
  * element out_off[f] of info_hat (all dev; the caller keeps the offsets inside
  * its buffers).  used_scl dev [B] or NULL; stats as in hybrid_decode_batch.
- * On the device the frames are bucketed by code; each code's BP is a
- * persistent kernel over its bucket that appends its failed frames to a queue
- * drained by the code's persistent CA-SCL kernel; the codes' chains are
- * concurrent branches on the plan's streams; a merge writes the results.
+ * On the device the frames are bucketed by block length (codes shorter than
+ * 32 bits: by code); each bucket's BP is a persistent kernel that decodes
+ * every frame with its own code and appends the failed frames to a queue
+ * drained by one persistent CA-SCL kernel, again per frame's code; the
+ * buckets' chains are concurrent branches on the plan's streams; a merge
+ * writes the results.
  * polar_mixed_decode enqueues the kernels; polar_mixed_decode_graph replays
  * the same work as one hipGraph, captured on its first call on the plan
  * (the kernels read the per-call buffers through a device argument block

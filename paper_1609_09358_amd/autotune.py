@@ -10,6 +10,7 @@ stream) and keeps the fastest; results are cached per process and optionally
 in a JSON file.
 """
 import json
+import time
 import os
 
 import torch
@@ -108,6 +109,31 @@ def tune_mixed(codes, llr_per_code, max_iter: int, L: int, scl_frames: int = 204
     b = tune_scl_budget(codes[c_big], sub, L)
     detail["scl"] = b
     return {"variants": variants, "budget": b["budget"], "detail": detail}
+
+
+def tune_mixed_budget(codes, args, max_iter: int, L: int, variants, budgets=(0, 12288, 16384, 24576, 40960),
+                      reps: int = 5) -> dict:
+    """The list decoder's LDS budget for a mixed plan, chosen by timing the
+    whole plan (replayed graph) on a batch: `args` = (llr, code_of_frame,
+    llr_off, out_off, info_hat, used).  A smaller budget fits more frames on a
+    CU at once, a larger one keeps more tree levels in LDS.  Returns
+    {"budget": ..., "ms": {...}}; the budget is left set."""
+    ms = {}
+    B = int(args[1].numel())
+    for b in budgets:
+        PB.polar_set_scl_lds_budget(b)
+        plan = PB.MixedPlan(codes, max_frames=B, max_iter=max_iter, L=L, variants=variants)
+        plan(*args, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan(*args, graph=True)
+        torch.cuda.synchronize()
+        ms[b] = (time.perf_counter() - t0) / reps * 1e3
+        del plan
+    best = min(ms, key=ms.get)
+    PB.polar_set_scl_lds_budget(best)
+    return {"budget": best, "ms": {str(k): round(v, 3) for k, v in ms.items()}}
 
 
 def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=(0, 4, 6, 8), steps: int = 6) -> dict:

@@ -481,6 +481,8 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
 // (the count lives on the device); frame id's LLR row starts at element
 // io->off[id] of io->llr, its u_hat row at id * u_stride; iters and ok are
 // indexed by id; failed frames are appended to fail_ids (one atomic each).
+// With io->codes, frame id uses the code io->codes[io->code_of[id]] (all of
+// the kernel's block length).
 template <int NLOG, int RLOG, bool WEIGHTED>
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
     CodeDev code, const MixedIo* __restrict__ mio, const int32_t* __restrict__ ids, const int32_t* __restrict__ count,
@@ -501,6 +503,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
         if (G::T >= 64) __syncthreads();  // the previous frame's staging is read
         if (q >= cnt) break;             // only when T < 64: this slot's wavefront lanes leave alone
         const int id = ids[q];
+        const CodeDev cd = mio->codes ? mio->codes[mio->code_of[id]] : code;
         FrameIO io;
         io.llr = llr + off[id];
         io.u_hat = u_hat + (int64_t)id * u_stride;
@@ -508,7 +511,7 @@ __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
         io.iters = iters_out + id;
         io.ok = ok_out + id;
         io.saved = nullptr;
-        const bool okv = bp_frame<G, WEIGHTED, false>(code, io, max_iter, stop, lmax, W, sh, t, slot);
+        const bool okv = bp_frame<G, WEIGHTED, false>(cd, io, max_iter, stop, lmax, W, sh, t, slot);
         if (t == 0 && !okv) fail_ids[atomicAdd(fail_count, 1)] = id;
     }
 }

@@ -96,6 +96,10 @@ polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B,
 struct MixedIo {
     const float* llr;     // LLR rows
     const int64_t* off;   // row of frame f starts at element off[f]
+    // several codes in one launch (or null): frame f is decoded with
+    // codes[code_of[f]] instead of the kernel's code argument
+    const int32_t* code_of;
+    const CodeDev* codes;
 };
 
 // persistent BP over a device list of frame ids with ragged row offsets;
@@ -118,8 +122,11 @@ struct SclPlan {
     size_t trace_off;    // byte offset of the trace inside the global slice
     size_t glob_per_wg;  // global slice bytes per workgroup (levels >= gl, trace)
     int grid;            // workgroups launched
+    int lay_n;           // log2 of the largest block length the layout holds
 };
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan);
+// a plan that holds any code with n <= max_n (n >= 5) and k <= max_k
+polar_status scl_plan_dims(int max_n, int max_k, int L, int64_t max_frames, SclPlan* plan);
 // io (optional): LLR rows of a ragged batch (frame f at element io->off[f]),
 // u_hat rows then at f * u_stride
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,

@@ -4,12 +4,14 @@
 // A call: a one-thread kernel stores the call's arguments in a device block;
 // counters are cleared by a kernel (no memset node, so the pipeline can be
 // captured); a bucketing kernel appends every frame id to the list of its
-// code; the codes' chains then run as concurrent branches on the plan's
-// streams: a persistent BP kernel walks the code's list (its length read on
-// the device), appending the frames whose verdict is not ok to the code's
-// queue, and the persistent CA-SCL kernel drains that queue; after the
-// branches join, a merge kernel writes every frame's information bits, its
-// list-decoder flag and the statistics.  No host round trip and no per-call
+// block length; then, per block length, as concurrent branches on the plan's
+// streams: a persistent BP kernel walks the list (its length read on the
+// device) decoding every frame with its own code and appends the frames whose
+// verdict is not ok to the group's queue, and a persistent CA-SCL kernel
+// drains that queue, again with each frame's own code (its layout holds the
+// group's largest information set).  After the branches join, a merge kernel
+// writes every frame's information bits, its list-decoder flag and the
+// statistics.  (Codes shorter than 32 bits form one group each.)  No host round trip and no per-call
 // allocation: the plan owns its workspace.  Because the kernels read the
 // per-call buffers through the argument block, the same captured graph
 // serves every call.
@@ -42,14 +44,16 @@ __global__ void clear_kernel(int32_t* c, int n) {
     if ((int)lid_x() < n) c[lid_x()] = 0;
 }
 
-// ids of code c: lists[c * cap + ...], cnt[c] of them
+// ids of group g (the group of the frame's code): lists[g * cap + ...], cnt[g] of them
 __global__ __launch_bounds__(256) void bucket_kernel(const MixedArgs* __restrict__ a, int n_codes, int64_t cap,
+                                                     const int32_t* __restrict__ group_of_code,
                                                      int32_t* __restrict__ lists, int32_t* __restrict__ cnt) {
     const int64_t f = gid_x() * wg_size_x() + lid_x();
     if (f >= a->B || f >= cap) return;
     const int c = a->code_of_frame[f];
     if (c < 0 || c >= n_codes) return;
-    lists[(int64_t)c * cap + atomicAdd(&cnt[c], 1)] = (int32_t)f;
+    const int g = group_of_code[c];
+    lists[(int64_t)g * cap + atomicAdd(&cnt[g], 1)] = (int32_t)f;
 }
 
 // one wavefront per frame
@@ -92,21 +96,25 @@ struct polar_mixed {
     int L = 0;
     int maxN = 0;
     std::vector<const polar_code*> codes;
-    std::vector<bp_params> params;  // per code (variant)
-    std::vector<SclPlan> scl;
-    std::vector<int> bp_grid;
+    // groups: codes of one block length (one code each below 32 bits)
+    int n_groups = 0;
+    std::vector<int> rep;           // per group: its first code
+    std::vector<bp_params> params;  // per group (the first code's variant)
+    std::vector<SclPlan> scl;       // per group
+    std::vector<int> bp_grid;       // per group
     // device memory (one allocation)
     void* mem = nullptr;
     MixedArgs* dargs = nullptr;
     CodeDev* dcodes = nullptr;
+    int32_t* gmap = nullptr;    // [n_codes] group of each code
     int32_t* counts = nullptr;  // [2 * n_codes]: bucket sizes, then queue sizes
-    int32_t* lists = nullptr;   // [n_codes][cap]
-    int32_t* queues = nullptr;  // [n_codes][cap]
+    int32_t* lists = nullptr;   // [n_groups][cap]
+    int32_t* queues = nullptr;  // [n_groups][cap]
     uint8_t* ok = nullptr;
     int32_t* iters = nullptr;
     uint8_t* scl_ok = nullptr;
     uint8_t* u = nullptr;  // [cap][maxN]
-    std::vector<void*> glob;  // per code list-decoder slice
+    std::vector<void*> glob;  // per list-decoder launch: its global slice
     int nbr = 0;
     hipStream_t br[kMaxBranches] = {};
     hipEvent_t ev_fork = nullptr;
@@ -160,24 +168,44 @@ extern "C" polar_status polar_mixed_create(const polar_code* const* codes, int32
             mixed_release(m);
             return set_error(POLAR_ERR_INVALID_ARG, "polar_mixed_create: CRC stop needs codes with a CRC");
         }
-        bp_params p = *params;
-        p.variant = variants ? variants[c] : 0;
-        if (p.variant != 0 && !bp_variant_supported(code->n, p.variant)) {
+        const int v = variants ? variants[c] : 0;
+        if (v != 0 && !bp_variant_supported(code->n, v)) {
             mixed_release(m);
             return set_error(POLAR_ERR_INVALID_ARG, "polar_mixed_create: unknown BP variant");
         }
+        m->codes.push_back(code);
+        if (code->N > m->maxN) m->maxN = code->N;
+    }
+    // groups: one per block length (one BP kernel and one list-decoder kernel
+    // serve the group's codes); a code shorter than 32 bits forms its own
+    std::vector<int32_t> gmap(n_codes);
+    for (int c = 0; c < n_codes; ++c) {
+        int g = -1;
+        if (codes[c]->n >= 5)
+            for (int h = 0; h < m->n_groups; ++h)
+                if (codes[m->rep[h]]->N == codes[c]->N) g = h;
+        if (g < 0) {
+            g = m->n_groups++;
+            m->rep.push_back(c);
+        }
+        gmap[c] = g;
+    }
+    for (int g = 0; g < m->n_groups; ++g) {
+        const int c = m->rep[g];
+        bp_params p = *params;
+        p.variant = variants ? variants[c] : 0;
+        int grid = 0, max_k = 0;
+        for (int c2 = 0; c2 < n_codes; ++c2)
+            if (gmap[c2] == g && codes[c2]->k > max_k) max_k = codes[c2]->k;
         SclPlan sp;
-        int grid = 0;
-        if ((st = scl_plan(code, L, max_frames, &sp)) != POLAR_OK ||
-            (st = bp_gather_grid(code, &p, max_frames, &grid)) != POLAR_OK) {
+        if ((st = bp_gather_grid(codes[c], &p, max_frames, &grid)) != POLAR_OK ||
+            (st = scl_plan_dims(codes[c]->n, max_k, L, max_frames, &sp)) != POLAR_OK) {
             mixed_release(m);
             return st;
         }
-        m->codes.push_back(code);
         m->params.push_back(p);
-        m->scl.push_back(sp);
         m->bp_grid.push_back(grid);
-        if (code->N > m->maxN) m->maxN = code->N;
+        m->scl.push_back(sp);
     }
     // one device allocation, carved
     size_t off = 0;
@@ -188,15 +216,16 @@ extern "C" polar_status polar_mixed_create(const polar_code* const* codes, int32
     };
     const size_t o_args = take(sizeof(MixedArgs));
     const size_t o_codes = take(sizeof(CodeDev) * n_codes);
+    const size_t o_gmap = take(sizeof(int32_t) * n_codes);
     const size_t o_cnt = take(sizeof(int32_t) * 2 * n_codes);
-    const size_t o_lists = take(sizeof(int32_t) * n_codes * max_frames);
-    const size_t o_queues = take(sizeof(int32_t) * n_codes * max_frames);
+    const size_t o_lists = take(sizeof(int32_t) * m->n_groups * max_frames);
+    const size_t o_queues = take(sizeof(int32_t) * m->n_groups * max_frames);
     const size_t o_ok = take(max_frames);
     const size_t o_it = take(sizeof(int32_t) * max_frames);
     const size_t o_sok = take(max_frames);
     const size_t o_u = take((size_t)m->maxN * max_frames);
-    std::vector<size_t> o_g(n_codes);
-    for (int c = 0; c < n_codes; ++c) o_g[c] = take(m->scl[c].glob_per_wg * m->scl[c].grid);
+    std::vector<size_t> o_g(m->scl.size());
+    for (size_t j = 0; j < m->scl.size(); ++j) o_g[j] = take(m->scl[j].glob_per_wg * m->scl[j].grid);
     if ((st = hip_check(hipMalloc(&m->mem, off), "polar_mixed_create: hipMalloc")) != POLAR_OK) {
         m->mem = nullptr;
         mixed_release(m);
@@ -205,6 +234,7 @@ extern "C" polar_status polar_mixed_create(const polar_code* const* codes, int32
     char* b = static_cast<char*>(m->mem);
     m->dargs = reinterpret_cast<MixedArgs*>(b + o_args);
     m->dcodes = reinterpret_cast<CodeDev*>(b + o_codes);
+    m->gmap = reinterpret_cast<int32_t*>(b + o_gmap);
     m->counts = reinterpret_cast<int32_t*>(b + o_cnt);
     m->lists = reinterpret_cast<int32_t*>(b + o_lists);
     m->queues = reinterpret_cast<int32_t*>(b + o_queues);
@@ -212,11 +242,13 @@ extern "C" polar_status polar_mixed_create(const polar_code* const* codes, int32
     m->iters = reinterpret_cast<int32_t*>(b + o_it);
     m->scl_ok = reinterpret_cast<uint8_t*>(b + o_sok);
     m->u = reinterpret_cast<uint8_t*>(b + o_u);
-    for (int c = 0; c < n_codes; ++c) m->glob.push_back(m->scl[c].glob_per_wg ? (void*)(b + o_g[c]) : nullptr);
+    for (size_t j = 0; j < m->scl.size(); ++j) m->glob.push_back(m->scl[j].glob_per_wg ? (void*)(b + o_g[j]) : nullptr);
     std::vector<CodeDev> hc(n_codes);
     for (int c = 0; c < n_codes; ++c) hc[c] = codes[c]->dev();
     st = hip_check(hipMemcpy(m->dcodes, hc.data(), sizeof(CodeDev) * n_codes, hipMemcpyHostToDevice), "copy codes");
-    m->nbr = n_codes < kMaxBranches ? n_codes : kMaxBranches;
+    if (st == POLAR_OK)
+        st = hip_check(hipMemcpy(m->gmap, gmap.data(), sizeof(int32_t) * n_codes, hipMemcpyHostToDevice), "copy map");
+    m->nbr = m->n_groups < kMaxBranches ? m->n_groups : kMaxBranches;
     for (int s = 0; s < m->nbr && st == POLAR_OK; ++s) {
         st = hip_check(hipStreamCreateWithFlags(&m->br[s], hipStreamNonBlocking), "stream create");
         if (st == POLAR_OK) st = hip_check(hipEventCreateWithFlags(&m->ev_join[s], hipEventDisableTiming), "event");
@@ -244,23 +276,25 @@ extern "C" void polar_mixed_free(polar_mixed* m) {
 // everything after the argument block, on `st` (with branches on the plan's streams)
 static polar_status mixed_pipeline(polar_mixed* m, hipStream_t st) {
     polar_status r;
-    const int nc = m->n_codes;
+    const int nc = m->n_codes, ng = m->n_groups;
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, st, m->counts, 2 * nc);
     const unsigned bgrid = (unsigned)((m->cap + 255) / 256);
-    hipLaunchKernelGGL(bucket_kernel, dim3(bgrid), dim3(256), 0, st, m->dargs, nc, m->cap, m->lists, m->counts);
+    hipLaunchKernelGGL(bucket_kernel, dim3(bgrid), dim3(256), 0, st, m->dargs, nc, m->cap, m->gmap, m->lists,
+                       m->counts);
     if ((r = hip_check(hipGetLastError(), "bucket launch")) != POLAR_OK) return r;
     if ((r = hip_check(hipEventRecord(m->ev_fork, st), "event record")) != POLAR_OK) return r;
     for (int s = 0; s < m->nbr; ++s)
         if ((r = hip_check(hipStreamWaitEvent(m->br[s], m->ev_fork, 0), "stream wait")) != POLAR_OK) return r;
-    for (int c = 0; c < nc; ++c) {
-        hipStream_t bs = m->br[c % m->nbr];
-        const polar_code* code = m->codes[c];
-        if ((r = launch_bp_gather(code, &m->dargs->io, m->lists + (int64_t)c * m->cap, m->counts + c, &m->params[c],
-                                  m->u, m->maxN, m->iters, m->ok, m->queues + (int64_t)c * m->cap,
-                                  m->counts + nc + c, m->bp_grid[c], bs)) != POLAR_OK)
+    for (int g = 0; g < ng; ++g) {
+        hipStream_t bs = m->br[g % m->nbr];
+        const polar_code* code = m->codes[m->rep[g]];
+        int32_t* queue = m->queues + (int64_t)g * m->cap;
+        int32_t* qcount = m->counts + nc + g;
+        if ((r = launch_bp_gather(code, &m->dargs->io, m->lists + (int64_t)g * m->cap, m->counts + g, &m->params[g],
+                                  m->u, m->maxN, m->iters, m->ok, queue, qcount, m->bp_grid[g], bs)) != POLAR_OK)
             return r;
-        if ((r = launch_scl(code, m->scl[c], nullptr, m->L, m->queues + (int64_t)c * m->cap, m->counts + nc + c, 0,
-                            m->u, m->scl_ok, nullptr, m->glob[c], bs, &m->dargs->io, m->maxN)) != POLAR_OK)
+        if ((r = launch_scl(code, m->scl[g], nullptr, m->L, queue, qcount, 0, m->u, m->scl_ok, nullptr, m->glob[g], bs,
+                            &m->dargs->io, m->maxN)) != POLAR_OK)
             return r;
     }
     for (int s = 0; s < m->nbr; ++s) {
@@ -286,6 +320,8 @@ static polar_status mixed_set_args(polar_mixed* m, int64_t B, const float* llr, 
     MixedArgs a;
     a.io.llr = llr;
     a.io.off = llr_off;
+    a.io.code_of = code_of_frame;
+    a.io.codes = m->dcodes;
     a.B = B;
     a.code_of_frame = code_of_frame;
     a.out_off = out_off;

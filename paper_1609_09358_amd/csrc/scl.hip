@@ -234,7 +234,7 @@ struct Layout {
 };
 
 template <int L, int BL, bool BITONIC = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code, const float* __restrict__ llr,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code_in, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
                                                  uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
@@ -243,7 +243,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     constexpr int BS = 1 << BL;  // bits per block
     extern __shared__ __attribute__((aligned(16))) unsigned char sm[];
     const int lane = lid_x();
-    const int n = code.n, N = code.N;
     const int gl = lay.gl, SL = lay.sl, PW = lay.pw;
 
     float* slam = reinterpret_cast<float*>(sm);                   // [L][SL]
@@ -261,6 +260,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     const int64_t* const row_off = mio ? mio->off : nullptr;
     for (int64_t q = gid_x(); q < count; q += num_groups_x()) {
         const int64_t f = frame_ids ? (int64_t)frame_ids[q] : q;
+        // the frame's code (several codes in one launch: the layout holds the
+        // largest; level offsets inside a slot do not depend on n)
+        const CodeDev code = (mio && mio->codes) ? mio->codes[mio->code_of[f]] : code_in;
+        const int n = code.n, N = code.N;
         // rows of frame f: LLRs at row_off[f] (ragged batch) or f * N; u_hat at
         // f * u_stride (ragged batch) or f * N
         const float* chan = llr_base + (row_off ? row_off[f] : f * N);
@@ -628,7 +631,11 @@ static std::atomic<int64_t> g_scl_lds_budget{0};
 constexpr size_t kLdsPerCu = 160 * 1024;
 
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan) {
-    const int n = code->n, N = code->N, k = code->k;
+    return scl_plan_dims(code->n, code->k, L, max_frames, plan);
+}
+
+polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* plan) {
+    const int N = 1 << n;
     scl::KernelFn fn = scl::pick(L, n, use_bitonic(L));
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
     const int gl_min = n < 6 ? n : 6;
@@ -665,6 +672,7 @@ polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan
     plan->trace_off = lam_b;
     plan->glob_per_wg = align_up(lam_b + (tg ? (size_t)k * L : 0), 256);
     plan->grid = (int)grid;
+    plan->lay_n = n;
     return POLAR_OK;
 }
 
@@ -672,11 +680,11 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host, uint8_t* u_hat,
                         uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream, const MixedIo* io,
                         int64_t u_stride) {
-    scl::KernelFn fn = scl::pick(L, code->n, use_bitonic(L));
+    scl::KernelFn fn = scl::pick(L, plan.lay_n, use_bitonic(L));
     scl::Layout lay;
     lay.gl = plan.gl;
-    lay.sl = scl::slot_floats(code->n, plan.gl);
-    lay.pw = scl::ps_words(code->n);
+    lay.sl = scl::slot_floats(plan.lay_n, plan.gl);
+    lay.pw = scl::ps_words(plan.lay_n);
     lay.tg = plan.trace_glob;
     lay.tchunk = plan.trace_chunk;
     lay.gbytes = (int64_t)plan.glob_per_wg;

@@ -151,3 +151,30 @@ def test_autotuned_plan_decodes_identically():
         assert torch.equal(out0, out1)
     finally:
         PB.polar_set_scl_lds_budget(0)
+
+
+def test_mixed_short_codes_take_their_own_branch():
+    """Codes shorter than 32 bits form one group each; codes of one block
+    length share a group (one BP kernel and one list decoder, each frame with
+    its own code).  Every frame must match the single-code hybrid."""
+    from paper_1609_09358_amd import mixed_workload as MW
+    codes = [PB.PolarCode(16, 4, 8, 0, 2.0), PB.PolarCode(8, 2, 0, 0, 2.0),
+             PB.PolarCode(256, 64, 8, 0, 2.0), PB.PolarCode(256, 160, 8, 0, 2.0)]
+    it, L, B = 30, 4, 500
+    batch = MW.ragged_batch(codes, B, seed=31)
+    plan = PB.MixedPlan(codes, max_frames=B, max_iter=it, L=L)
+    info_hat = torch.full((batch["total_info_bits"],), 7, dtype=torch.uint8, device="cuda")
+    used = torch.full((B,), 9, dtype=torch.uint8, device="cuda")
+    plan(batch["llr"], batch["code_of_frame"], batch["llr_off"], batch["out_off"], info_hat, used, graph=True)
+    torch.cuda.synchronize()
+    oo = batch["out_off"].cpu().numpy()
+    got_all, used_all = info_hat.cpu().numpy(), used.cpu().numpy()
+    for c, code in enumerate(codes):
+        ids, rows = batch["per_code"][c]
+        if ids.numel() == 0:
+            continue
+        one = PB.HybridDecoder(code, max_iter=it, L=L)(rows.contiguous())
+        idx = ids.cpu().numpy()
+        got = np.stack([got_all[oo[f]:oo[f] + code.K] for f in idx])
+        assert np.array_equal(got, one["info"].cpu().numpy()), f"code {c}"
+        assert np.array_equal(used_all[idx], one["used_scl"].cpu().numpy()), f"code {c}"
