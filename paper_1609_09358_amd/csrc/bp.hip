@@ -44,7 +44,7 @@ __device__ __forceinline__ uint64_t load_bits(const uint8_t* src) {
     return w;
 }
 
-// Packed u decisions (V = 8 and a frame of at least one wavefront): bit j of
+// Packed decisions (V = 8 and a frame of at least one wavefront): bit j of
 // the frame's bit array is node j.  Checker lane l's CB consecutive bits, read
 // in one access.
 template <class G>
@@ -73,7 +73,7 @@ constexpr uint64_t low_half_mask(int d) {
 template <class G, bool PACKED>
 __device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t* xb, int lane) {
     uint64_t u = lane_bits<G, PACKED>(ub, lane);
-    uint64_t x = load_bits<G>(xb + lane * G::CB);
+    uint64_t x = lane_bits<G, PACKED>(xb, lane);
     // butterflies inside a word: distances 1, 2, .. CB/2 (masks fixed at compile time)
     static_for<0, 6>([&](auto D) {
         constexpr int d = 1 << decltype(D)::value;
@@ -151,8 +151,10 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
     // min-sum inference takes the sign-transfer form of g; training (SAVE)
     // and the exact rule keep the direct form
     constexpr bool FAST = RULE == 0 && !SAVE;
-    // u decisions stored as bits, one byte per thread of window 0 (its eight
-    // consecutive nodes), instead of one byte each; x decisions stay bytes
+    // decisions stored as bits instead of one byte each (u: one byte per
+    // thread of window 0, its eight consecutive nodes; x: one ballot per
+    // register and wavefront, since in the last window a wavefront's lanes
+    // hold 64 consecutive nodes)
     constexpr bool BITPACK = G::V == 8 && G::T >= 64;
     float* tb = sh.tb;
     const int lane = (G::T < 64) ? t : (lid_x() & 63);
@@ -199,7 +201,6 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
 
     int it = 0;
     bool gok = false, cok = false;
-    float L0[V];
     while (true) {
         const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * (WSTAGE ? 1 : N) : nullptr;
         float* Sit = SAVE ? io.saved + (size_t)it * 2 * n * N : nullptr;
@@ -271,9 +272,22 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             }
         });
         if (stop != 2) {
-            const int ib = idx_base<G, KL>(t);
+            if constexpr (BITPACK) {
+                // thread t holds node t + (v << P): the wavefront's ballot for
+                // register v is 64-bit word (v << (P - 6)) + w of the array
+                uint64_t m[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) xb[ib + (v << G::wbase(KL))] = (Lm[n][v] + Rm[n][v]) < 0.0f ? 1 : 0;
+                for (int v = 0; v < V; ++v) m[v] = __ballot((Lm[n][v] + Rm[n][v]) < 0.0f);
+                if (lane == 0) {
+                    uint64_t* xw = reinterpret_cast<uint64_t*>(xb) + (t >> 6);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) xw[v << (G::P - 6)] = m[v];
+                }
+            } else {
+                const int ib = idx_base<G, KL>(t);
+#pragma unroll
+                for (int v = 0; v < V; ++v) xb[ib + (v << G::wbase(KL))] = (Lm[n][v] + Rm[n][v]) < 0.0f ? 1 : 0;
+            }
         }
         // ---------------- L sweep: columns n-1..0
         static_for_rev<0, G::NWIN>([&](auto KC) {
@@ -347,7 +361,6 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             uint32_t bits = 0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                L0[v] = Lm[0][v];
                 const float lu = Lm[0][v] + prior[v];
                 bits |= (((fmask >> v) & 1u) == 0 && lu < 0.0f) ? (1u << v) : 0u;
             }
@@ -356,7 +369,6 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             uint64_t pack = 0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                L0[v] = Lm[0][v];
                 const float lu = Lm[0][v] + prior[v];
                 const uint64_t bit = (((fmask >> v) & 1u) == 0 && lu < 0.0f) ? 1ull : 0ull;
                 pack |= bit << (8 * v);
@@ -415,7 +427,9 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
         if (io.llr_u) {
             float* lo = io.llr_u + ib;
 #pragma unroll
-            for (int v = 0; v < V; ++v) lo[v] = L0[v] + prior[v];
+            // row 0 still holds the last iteration's L messages (the loop
+            // leaves right after the decisions that read it)
+            for (int v = 0; v < V; ++v) lo[v] = Lm[0][v] + prior[v];
         }
         if (t == 0) {
             if (io.iters) *io.iters = it;
