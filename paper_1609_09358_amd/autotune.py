@@ -111,29 +111,49 @@ def tune_mixed(codes, llr_per_code, max_iter: int, L: int, scl_frames: int = 204
     return {"variants": variants, "budget": b["budget"], "detail": detail}
 
 
-def tune_mixed_budget(codes, args, max_iter: int, L: int, variants, budgets=(0, 12288, 16384, 24576, 40960),
-                      reps: int = 5) -> dict:
-    """The list decoder's LDS budget for a mixed plan, chosen by timing the
-    whole plan (replayed graph) on a batch: `args` = (llr, code_of_frame,
-    llr_off, out_off, info_hat, used).  A smaller budget fits more frames on a
-    CU at once, a larger one keeps more tree levels in LDS.  Returns
-    {"budget": ..., "ms": {...}}; the budget is left set."""
-    ms = {}
+def tune_mixed_plan(codes, args, max_iter: int, L: int, variants, budgets=(0, 12288, 16384, 24576, 40960),
+                    reps: int = 5) -> dict:
+    """Whole-plan choices for a mixed plan, each timed on a batch (replayed
+    graph; `args` = (llr, code_of_frame, llr_off, out_off, info_hat, used)):
+    first the BP layout of the longest block length, whose bucket is the
+    critical path (its failing frames run every iteration; a layout with more
+    threads per frame shortens that chain even where it lowers throughput),
+    then the list decoder's LDS budget (a smaller one fits more frames on a CU
+    at once, a larger one keeps more tree levels in LDS).  Returns
+    {"variants": [...], "budget": ..., "ms": {...}}; the budget is left set."""
     B = int(args[1].numel())
-    for b in budgets:
-        PB.polar_set_scl_lds_budget(b)
-        plan = PB.MixedPlan(codes, max_frames=B, max_iter=max_iter, L=L, variants=variants)
+
+    def timed(var):
+        plan = PB.MixedPlan(codes, max_frames=B, max_iter=max_iter, L=L, variants=var)
         plan(*args, graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
             plan(*args, graph=True)
         torch.cuda.synchronize()
-        ms[b] = (time.perf_counter() - t0) / reps * 1e3
-        del plan
-    best = min(ms, key=ms.get)
-    PB.polar_set_scl_lds_budget(best)
-    return {"budget": best, "ms": {str(k): round(v, 3) for k, v in ms.items()}}
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    variants = list(variants)
+    ms = {}
+    nmax = max(c.N for c in codes)
+    PB.polar_set_scl_lds_budget(0)
+    best_v, best_t = None, None
+    for v in PB.polar_bp_variants(nmax):
+        var = [v if c.N == nmax else variants[i] for i, c in enumerate(codes)]
+        t = timed(var)
+        ms[f"variant_N{nmax}_{v}"] = round(t, 3)
+        if best_t is None or t < best_t:
+            best_v, best_t = v, t
+    variants = [best_v if c.N == nmax else variants[i] for i, c in enumerate(codes)]
+    best_b, best_bt = None, None
+    for b in budgets:
+        PB.polar_set_scl_lds_budget(b)
+        t = timed(variants)
+        ms[f"budget_{b}"] = round(t, 3)
+        if best_bt is None or t < best_bt:
+            best_b, best_bt = b, t
+    PB.polar_set_scl_lds_budget(best_b)
+    return {"variants": variants, "budget": best_b, "ms": ms}
 
 
 def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=(0, 4, 6, 8), steps: int = 6) -> dict:

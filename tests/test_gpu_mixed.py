@@ -149,6 +149,16 @@ def test_autotuned_plan_decodes_identically():
         plan(*args, out1, graph=True)
         torch.cuda.synchronize()
         assert torch.equal(out0, out1)
+        # whole-plan tuning (longest bucket's layout, LDS budget)
+        used = torch.empty(400, dtype=torch.uint8, device="cuda")
+        out2 = torch.empty_like(out0)
+        tp = autotune.tune_mixed_plan(codes, args + (out2, used), 50, 8, tuned["variants"], budgets=(0, 16384), reps=2)
+        assert all(v in PB.polar_bp_variants(c.N) for v, c in zip(tp["variants"], codes))
+        plan2 = PB.MixedPlan(codes, max_frames=400, max_iter=50, L=8, variants=tp["variants"])
+        out3 = torch.empty_like(out0)
+        plan2(*args, out3, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out0, out3)
     finally:
         PB.polar_set_scl_lds_budget(0)
 
