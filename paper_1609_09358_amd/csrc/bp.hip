@@ -17,10 +17,17 @@
 // When a frame needs fewer than 64 threads, one wavefront carries 64 / T
 // frames, each leaving the iteration loop on its own.
 //
+// PE arithmetic (min-sum inference): a PE's two g terms share one operand a,
+// and g(a, b) = sgn(a) clamp(b, -|a|, |a|), so the sign of a is moved once
+// into the weight and each g is one clamp; with one weight per stage column
+// and every weight within [-1, 1] a second copy of the decoder leaves out the
+// first output's clip, which cannot act there.
+//
 // Early stop (Sec. II-B): after each iteration the hard decisions on LLR(u)
-// and LLR(x) are packed into bit words (N / 64 bits per lane), u_hat is
-// re-encoded with shifts inside words and lane exchanges across words, and
-// compared with x_hat; the CRC test uses per-nibble syndrome tables.
+// and LLR(x) are stored as bits (eight-register layouts; bytes otherwise) and
+// gathered into words of N / 64 bits per checker lane, u_hat is re-encoded
+// with shifts inside words and lane exchanges across words, and compared with
+// x_hat; the CRC test uses per-nibble syndrome tables.
 #include "bp_common.hpp"
 
 namespace polarhip {
