@@ -310,6 +310,7 @@ def main():
     extra["c4_learned_bp"] = c4_learned_bp(frames=args.train_frames)
     extra["scl_ranking_ab"] = scl_ranking_ab(code, llr, bp_out, W, T)
     extra["latency"] = latency_study(code, learned, T, W)
+    extra["c5_other_points"] = c5_points(code, learned_pipe, plain_pipe, learned, plain, B)
     extra["c2_rules"] = c2_rules(args.frames, max(3, args.steps // 4))
     extra["paper_operating_point"] = paper_operating_point()
 
@@ -373,6 +374,40 @@ def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
             res[f"L{L}_{name}"] = dict(frames=int(ids.numel()), **row)
     PB.polar_set_scl_ranking(0)
     return res
+
+
+def c5_points(code, learned_pipe, plain_pipe, learned, plain, B, ebn0s=(2.0, 3.0), steps=10, fer_frames=1 << 18):
+    """The learned hybrid at the other Eb/N0 points of its configuration (the
+    weights fitted at 2.5 dB): pipelined throughput of both decoders on one
+    resident batch, and their FER on common fresh frames with the
+    Clopper-Pearson bound of the plain decoder's."""
+    import torch
+
+    from paper_1609_09358_amd import train_wbp as TW
+
+    rows = []
+    for e in ebn0s:
+        gen = TW.Trainer(code, 1, 16, seed=int(100 * e) + 17)
+        _, _, llr = gen.frames(B, ebn0=e)
+        res = {"ebn0_db": e}
+        for name, pipe in (("learned", learned_pipe), ("plain", plain_pipe)):
+            pipe([llr] * 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pipe([llr] * steps)
+            torch.cuda.synchronize()
+            res[f"{name}_Gbps"] = round(B * code.K * steps / (time.perf_counter() - t0) / 1e9, 4)
+        nf = el = ep = 0
+        while nf < fer_frames:
+            b = min(B, fer_frames - nf)
+            inf_f, _, llr_f = gen.frames(b, ebn0=e)
+            el += int((learned(llr_f)["info"] != inf_f).any(dim=1).sum())
+            ep += int((plain(llr_f)["info"] != inf_f).any(dim=1).sum())
+            nf += b
+        res.update(fer_frames=nf, fer_learned=el / nf, fer_plain=ep / nf, fer_plain_cp95_upper=cp_upper(ep, nf),
+                   valid_fer_le_plain=bool(el / nf <= cp_upper(ep, nf)))
+        rows.append(res)
+    return rows
 
 
 def latency_study(code, learned, T, W, reps=20):
