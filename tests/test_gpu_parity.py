@@ -70,7 +70,7 @@ def test_channel_matches_oracle():
 # ------------------------------------------------------------------ BP
 
 BP_CASES = [(8, 4, 0), (16, 8, 0), (64, 32, 0), (128, 64, 0), (256, 128, 8), (512, 256, 16), (1024, 512, 16),
-            (2048, 1024, 16)]
+            (2048, 1024, 16), (4096, 2048, 16)]
 
 
 @pytest.mark.parametrize("N,K,c", BP_CASES)
