@@ -8,7 +8,7 @@ One step is one hybrid decode of a resident batch of frames: weighted
 (learned) min-sum BP with at most T = 20 iterations (re-encoding stop, CRC
 verdict), device-side compaction of the frames whose verdict is not ok,
 CA-SCL with list size 32 on them (with the decision aiding of Sec. II-A on the
-256 most reliable information positions: on 39192 frames the learned BP
+320 most reliable information positions: on 39192 frames the learned BP
 failed at 2.5 dB it made the same frame errors as plain CA-SCL for every count
 up to 320), merge.  Steps run through the two-stream
 pipeline (BP and compaction of step j + 1 overlap the CA-SCL and merge of
@@ -110,7 +110,7 @@ def main():
     from paper_1609_09358_amd import train_wbp as TW
 
     torch.cuda.set_device(0)
-    N, K, C, DESIGN, T, L, IMAX, DA = 1024, 512, 24, 2.5, args.T, args.L, 200, 256
+    N, K, C, DESIGN, T, L, IMAX, DA = 1024, 512, 24, 2.5, args.T, args.L, 200, 320
     n = N.bit_length() - 1
     B = args.frames
     R = K / N

@@ -414,11 +414,11 @@ def test_plain_bp_c1_configuration_bit_exact():
 def test_learned_hybrid_full_size_pipelined_sampled():
     """The benchmark's learned hybrid at its full size and launch path: 65536
     frames at 2.5 dB through the two-stream pipeline, weighted BP T = 20 with one
-    weight per stage column, CA-SCL L = 32 with 256 decision-aided positions,
+    weight per stage column, CA-SCL L = 32 with 320 decision-aided positions,
     CRC-24; sampled frames (list-decoded ones included) against the oracle's
     float build with the same weights."""
     N, K, c, L, T, B = 1024, 512, 24, 32, 20, 65536
-    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=256)
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=320)
     info = inputs.info_bits(B, K, seed=2025)
     x = PB.polar_encode(code, dev(info))
     s2 = torch.full((B,), O.sigma2(2.5, 0.5), dtype=torch.float32, device="cuda")
