@@ -56,7 +56,7 @@ POLY24 = 0x864CFB
 # stage column), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size; valid only
 # for the kernel sources they were measured on (hash of the files below)
-BP_TRAFFIC = {"bytes": 349621453, "frames": 65536, "src_sha256_16": "c27810de7463fdb9"}
+BP_TRAFFIC = {"bytes": 349621453, "frames": 65536, "src_sha256_16": "5a64bcb9261ce622"}
 BP_SOURCES = ("paper_1609_09358_amd/csrc/bp.hip", "paper_1609_09358_amd/csrc/bp_common.hpp",
               "paper_1609_09358_amd/csrc/bp_geom.hpp")
 

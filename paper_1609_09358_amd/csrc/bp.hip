@@ -504,8 +504,15 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
 // indexed by id; failed frames are appended to fail_ids (one atomic each).
 // With io->codes, frame id uses the code io->codes[io->code_of[id]] (all of
 // the kernel's block length).
+// The unweighted N = 2048 gather kernel (256 threads per frame) fits three
+// waves per SIMD instead of two without spilling: its failing frames run every iteration, so more frames in
+// flight shorten the mixed batch's longest chain.
 template <int NLOG, int RLOG, bool WEIGHTED>
-__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG)) void bp_gather_kernel(
+constexpr int gather_waves_per_eu() { return (NLOG == 11 && RLOG == 3 && !WEIGHTED) ? 3 : 1; }
+
+template <int NLOG, int RLOG, bool WEIGHTED>
+__global__ __launch_bounds__((Geom<NLOG, RLOG>::WG))
+__attribute__((amdgpu_waves_per_eu(gather_waves_per_eu<NLOG, RLOG, WEIGHTED>()))) void bp_gather_kernel(
     CodeDev code, const MixedIo* __restrict__ mio, const int32_t* __restrict__ ids, const int32_t* __restrict__ count,
     int max_iter, int stop, float lmax, const float* __restrict__ W, uint8_t* __restrict__ u_hat, int64_t u_stride,
     int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, int32_t* __restrict__ fail_ids,
