@@ -217,7 +217,8 @@ polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64
  * stream_scl.
  * llr, info_hat, used_scl: host arrays of nbatch device pointers ([B][N],
  * [B][K], [B]; used_scl may be NULL or hold NULL entries); batches may share
- * an input buffer.  Results and stats (accumulated as in hybrid_decode_batch)
+ * an input buffer, not an output buffer (the BP of batch j + 1 writes its
+ * kept frames' information bits while batch j's list-decoded ones are merged).  Results and stats (accumulated as in hybrid_decode_batch)
  * are complete when work enqueued on stream_bp after the call completes:
  * stream_bp finally waits for stream_scl.  The two streams must differ.
  * ws: at least polar_pipeline_workspace_size(code, B, L, params) bytes.

@@ -162,13 +162,15 @@ def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=
     the fastest set.  Returns {"wgs_per_cu": best, "ms": {cap: ms per batch}}."""
     import time
     timings = {}
-    out = [dict(info=torch.empty((llr.shape[0], pipe.code.K), dtype=torch.uint8, device=llr.device))]
+    # two output buffers alternate: consecutive batches of a call must not share one
+    out = [dict(info=torch.empty((llr.shape[0], pipe.code.K), dtype=torch.uint8, device=llr.device)) for _ in range(2)]
+    alt = lambda k: [out[i % 2] for i in range(k)]
     for c in choices:
         PB.polar_set_pipeline_bp_occupancy(c)
-        pipe([llr] * 2, outs=out * 2)
+        pipe([llr] * 2, outs=alt(2))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pipe([llr] * steps, outs=out * steps)
+        pipe([llr] * steps, outs=alt(steps))
         torch.cuda.synchronize()
         timings[c] = (time.perf_counter() - t0) / steps * 1e3
     best = min(timings, key=timings.get)

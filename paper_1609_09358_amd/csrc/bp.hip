@@ -140,6 +140,7 @@ struct BpShared {
 struct FrameIO {
     const float* llr;   // [N] channel LLRs
     uint8_t* u_hat;     // [N] or null
+    uint8_t* info;      // [K] or null: information bits, written when the verdict is ok
     float* llr_u;       // [N] or null
     int32_t* iters;     // one value or null
     uint8_t* ok;        // one value or null
@@ -438,6 +439,13 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             // leaves right after the decisions that read it)
             for (int v = 0; v < V; ++v) lo[v] = Lm[0][v] + prior[v];
         }
+        if (io.info && okv) {
+            // the hybrid keeps BP's result: its information bits go out here
+            for (int q = t; q < code.K; q += G::T) {
+                const int pos = code.info_pos[q];
+                io.info[q] = BITPACK ? (uint8_t)((ub[pos >> 3] >> (pos & 7)) & 1u) : ub[pos];
+            }
+        }
         if (t == 0) {
             if (io.iters) *io.iters = it;
             if (io.ok) *io.ok = (uint8_t)okv;
@@ -460,8 +468,9 @@ template <int NLOG, int RLOG, bool WEIGHTED, bool SAVE, int RULE = 0, bool WSTAG
 __global__ __launch_bounds__((Geom<NLOG, RLOG>::WG))
 __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, WSTAGE, PERSIST>()))) void bp_kernel(
     CodeDev code, const float* __restrict__ llr, int64_t B, int max_iter, int stop, float lmax,
-    const float* __restrict__ W, uint8_t* __restrict__ u_hat, float* __restrict__ llr_u,
-    int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out, float* __restrict__ saved) {
+    const float* __restrict__ W, uint8_t* __restrict__ u_hat, uint8_t* __restrict__ info_out,
+    float* __restrict__ llr_u, int32_t* __restrict__ iters_out, uint8_t* __restrict__ ok_out,
+    float* __restrict__ saved) {
     using G = Geom<NLOG, RLOG>;
     constexpr int N = G::N;
     __shared__ BpShared<G> sh;
@@ -484,6 +493,7 @@ __attribute__((amdgpu_waves_per_eu(bp_waves_per_eu<NLOG, RLOG, WEIGHTED, SAVE, W
         FrameIO io;
         io.llr = llr + frame * N;
         io.u_hat = u_hat ? u_hat + frame * N : nullptr;
+        io.info = info_out ? info_out + frame * code.K : nullptr;
         io.llr_u = llr_u ? llr_u + frame * N : nullptr;
         io.iters = iters_out ? iters_out + frame : nullptr;
         io.ok = ok_out ? ok_out + frame : nullptr;
@@ -535,6 +545,7 @@ __attribute__((amdgpu_waves_per_eu(gather_waves_per_eu<NLOG, RLOG, WEIGHTED>()))
         FrameIO io;
         io.llr = llr + off[id];
         io.u_hat = u_hat + (int64_t)id * u_stride;
+        io.info = nullptr;
         io.llr_u = nullptr;
         io.iters = iters_out + id;
         io.ok = ok_out + id;
@@ -546,8 +557,8 @@ __attribute__((amdgpu_waves_per_eu(gather_waves_per_eu<NLOG, RLOG, WEIGHTED>()))
 
 // ------------------------------------------------------------------ dispatch
 
-using KernelFn = void (*)(CodeDev, const float*, int64_t, int, int, float, const float*, uint8_t*, float*,
-                          int32_t*, uint8_t*, float*);
+using KernelFn = void (*)(CodeDev, const float*, int64_t, int, int, float, const float*, uint8_t*, uint8_t*,
+                          float*, int32_t*, uint8_t*, float*);
 
 using GatherFn = void (*)(CodeDev, const MixedIo*, const int32_t*, const int32_t*, int, int, float, const float*,
                           uint8_t*, int64_t, int32_t*, uint8_t*, int32_t*, int32_t*);
@@ -608,7 +619,8 @@ int bp_list_variants(int n, int32_t* ids, int cap) {
 }
 
 polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p, uint8_t* u_hat,
-                       float* llr_u, int32_t* iters, uint8_t* ok, hipStream_t stream, int wgs_per_cu) {
+                       float* llr_u, int32_t* iters, uint8_t* ok, hipStream_t stream, int wgs_per_cu,
+                       uint8_t* info_out) {
     const int variant = p->variant ? p->variant : bp_default_variant(code->n);
     const bp::Entry* e = bp::lookup(code->n, variant);
     if (!e) return set_error(POLAR_ERR_UNSUPPORTED, "bp: no kernel variant for this block length");
@@ -629,7 +641,7 @@ polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, cons
         }
     }
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(e->wg), 0, stream, code->dev(), llr, B, p->max_iter, p->stop,
-                       p->llr_max, p->weights, u_hat, llr_u, iters, ok, (float*)nullptr);
+                       p->llr_max, p->weights, u_hat, info_out, llr_u, iters, ok, (float*)nullptr);
     return hip_check(hipGetLastError(), "bp_kernel launch");
 }
 
@@ -669,7 +681,7 @@ polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B,
     const int64_t blocks = (B + e->fpw - 1) / e->fpw;
     bp::KernelFn fn = saved ? e->weighted_save : e->weighted;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(e->wg), 0, stream, code->dev(), llr, B, T, 0, llr_max, W,
-                       u_hat, llr_u, (int32_t*)nullptr, ok, saved);
+                       u_hat, (uint8_t*)nullptr, llr_u, (int32_t*)nullptr, ok, saved);
     return hip_check(hipGetLastError(), "bp_kernel launch");
 }
 

@@ -1,10 +1,11 @@
 // hybrid.hip -- hybrid BP -> CA-SCL decoder (Sec. III, Fig. 3).
 //
-// The CPU scheduling loop of Fig. 3 becomes four kernels on one stream with
-// no host round trip: BP on every frame, compaction of the frames whose BP
-// verdict is not ok into a device queue ("copy failed CWs to buffer"),
-// persistent CA-SCL workgroups that read the queue length on the device, and
-// a merge that emits the information bits and statistics.
+// The CPU scheduling loop of Fig. 3 becomes a few kernels on one stream with
+// no host round trip: BP on every frame (it writes the information bits of
+// the frames it keeps), compaction of the frames whose BP verdict is not ok
+// into a device queue ("copy failed CWs to buffer"), persistent CA-SCL
+// workgroups that read the queue length on the device, a pass over the flags
+// and statistics, and a merge of the list-decoded frames' information bits.
 #include <atomic>
 
 #include "internal.hpp"
@@ -29,53 +30,54 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict_
     if (fail) queue[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)f;
 }
 
-// info_hat <- information bits of u_hat (BP result or its SCL replacement);
-// 32 frames per workgroup, statistics reduced per wavefront before the atomics
-constexpr int kMergeFrames = 32;
-
-__global__ __launch_bounds__(256) void merge_kernel(CodeDev code, const uint8_t* __restrict__ u_hat,
-                                                    const uint8_t* __restrict__ ok,
-                                                    const int32_t* __restrict__ iters,
-                                                    const uint8_t* __restrict__ scl_ok, int64_t B,
-                                                    uint8_t* __restrict__ info_hat, uint8_t* __restrict__ used_scl,
+// used_scl and the statistics of every frame, reduced per wavefront before
+// the atomics (the information bits of the frames BP kept were written by the
+// BP kernel)
+__global__ __launch_bounds__(256) void flags_kernel(const uint8_t* __restrict__ ok,
+                                                    const int32_t* __restrict__ iters, int64_t B,
+                                                    uint8_t* __restrict__ used_scl,
                                                     unsigned long long* __restrict__ stats) {
-    const int K = code.K, N = code.N;
-    const int64_t f0 = gid_x() * kMergeFrames;
-    const int nf = (int)((B - f0) < kMergeFrames ? (B - f0) : kMergeFrames);
-    for (int it = lid_x(); it < nf * K; it += wg_size_x()) {
-        const int lf = it / K, q = it - lf * K;
-        const int64_t f = f0 + lf;
-        info_hat[f * K + q] = u_hat[f * N + code.info_pos[q]];
+    const int64_t f = gid_x() * 256 + lid_x();
+    unsigned long long s_n = 0, s_bp = 0, s_scl = 0, s_it = 0;
+    if (f < B) {
+        const bool good = ok[f] != 0;
+        if (used_scl) used_scl[f] = good ? 0 : 1;
+        s_n = 1;
+        s_bp = good;
+        s_scl = !good;
+        s_it = (unsigned long long)iters[f];
     }
-    if (lid_x() < 64) {
-        const int lf = lid_x();
-        unsigned long long s_bp = 0, s_scl = 0, s_it = 0, s_fail = 0, s_n = 0;
-        if (lf < nf) {
-            const int64_t f = f0 + lf;
-            const bool good = ok[f] != 0;
-            if (used_scl) used_scl[f] = good ? 0 : 1;
-            s_n = 1;
-            s_bp = good;
-            s_scl = !good;
-            s_it = (unsigned long long)iters[f];
-            s_fail = (!good && !scl_ok[f]) ? 1ull : 0ull;
+    if (stats) {
+        for (int m = 32; m >= 1; m >>= 1) {
+            s_n += __shfl_xor(s_n, m, 64);
+            s_bp += __shfl_xor(s_bp, m, 64);
+            s_scl += __shfl_xor(s_scl, m, 64);
+            s_it += __shfl_xor(s_it, m, 64);
         }
-        if (stats) {
-            for (int m = 32; m >= 1; m >>= 1) {
-                s_n += __shfl_xor(s_n, m, 64);
-                s_bp += __shfl_xor(s_bp, m, 64);
-                s_scl += __shfl_xor(s_scl, m, 64);
-                s_it += __shfl_xor(s_it, m, 64);
-                s_fail += __shfl_xor(s_fail, m, 64);
-            }
-            if (lf == 0) {
-                atomicAdd(&stats[0], s_n);
-                if (s_bp) atomicAdd(&stats[1], s_bp);
-                if (s_scl) atomicAdd(&stats[2], s_scl);
-                atomicAdd(&stats[3], s_it);
-                if (s_fail) atomicAdd(&stats[4], s_fail);
-            }
+        if ((lid_x() & 63) == 0 && s_n) {
+            atomicAdd(&stats[0], s_n);
+            if (s_bp) atomicAdd(&stats[1], s_bp);
+            if (s_scl) atomicAdd(&stats[2], s_scl);
+            atomicAdd(&stats[3], s_it);
         }
+    }
+}
+
+// information bits of the list-decoded frames queue[0 .. *count), one
+// workgroup per frame (persistent over the count on the device), and the
+// count of those whose CRC failed
+__global__ __launch_bounds__(256) void merge_scl_kernel(CodeDev code, const uint8_t* __restrict__ u_hat,
+                                                        const int32_t* __restrict__ queue,
+                                                        const int32_t* __restrict__ count,
+                                                        const uint8_t* __restrict__ scl_ok,
+                                                        uint8_t* __restrict__ info_hat,
+                                                        unsigned long long* __restrict__ stats) {
+    const int K = code.K, N = code.N;
+    const int64_t cnt = *count;
+    for (int64_t i = gid_x(); i < cnt; i += num_groups_x()) {
+        const int64_t f = queue[i];
+        for (int q = lid_x(); q < K; q += 256) info_hat[f * K + q] = u_hat[f * N + code.info_pos[q]];
+        if (lid_x() == 0 && stats && !scl_ok[f]) atomicAdd(&stats[4], 1ull);
     }
 }
 
@@ -156,10 +158,11 @@ polar_status pipeline_events(hipEvent_t** out) {
     return POLAR_OK;
 }
 
-// BP and compaction of one batch on `stream`
+// BP (writing the information bits of the frames it keeps straight to
+// info_hat) and compaction of one batch on `stream`
 polar_status enqueue_bp_part(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
-                             const HybridWs& w, hipStream_t stream, int wgs_per_cu = 0) {
-    polar_status st = launch_bp(code, llr, B, p, w.u_hat, nullptr, w.iters, w.ok, stream, wgs_per_cu);
+                             const HybridWs& w, uint8_t* info_hat, hipStream_t stream, int wgs_per_cu = 0) {
+    polar_status st = launch_bp(code, llr, B, p, nullptr, nullptr, w.iters, w.ok, stream, wgs_per_cu, info_hat);
     if (st != POLAR_OK) return st;
     hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(64), 0, stream, w.count);
     const unsigned cblocks = (unsigned)((B + 255) / 256);
@@ -174,9 +177,12 @@ polar_status enqueue_scl_part(const polar_code* code, const SclPlan& plan, const
     polar_status st = launch_scl(code, plan, llr, L, w.queue, w.count, 0, w.u_hat, w.scl_ok, nullptr, w.scl_glob,
                                  stream);
     if (st != POLAR_OK) return st;
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((B + kMergeFrames - 1) / kMergeFrames)), dim3(256), 0, stream,
-                       code->dev(), w.u_hat, w.ok, w.iters, w.scl_ok, B, info_hat, used_scl,
-                       reinterpret_cast<unsigned long long*>(stats));
+    unsigned long long* st64 = reinterpret_cast<unsigned long long*>(stats);
+    hipLaunchKernelGGL(flags_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, w.ok, w.iters, B,
+                       used_scl, st64);
+    const int64_t mgrid = B < 4096 ? B : 4096;
+    hipLaunchKernelGGL(merge_scl_kernel, dim3((unsigned)mgrid), dim3(256), 0, stream, code->dev(), w.u_hat, w.queue,
+                       w.count, w.scl_ok, info_hat, st64);
     return hip_check(hipGetLastError(), "merge launch");
 }
 
@@ -235,7 +241,7 @@ extern "C" polar_status hybrid_decode_batch(const polar_code* code, const float*
     if (B == 0) return ok_status();
     HybridWs w;
     carve(code, B, plan, ws, &w, 1);
-    if ((st = enqueue_bp_part(code, llr, B, p, w, stream)) != POLAR_OK) return st;
+    if ((st = enqueue_bp_part(code, llr, B, p, w, info_hat, stream)) != POLAR_OK) return st;
     if ((st = enqueue_scl_part(code, plan, llr, B, L, w, info_hat, used_scl, stats, stream)) != POLAR_OK) return st;
     return ok_status();
 }
@@ -273,7 +279,7 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
     for (int64_t j = 0; j < nbatch && st == POLAR_OK; ++j) {
         const int s = (int)(j % kPipeSlots);
         if (j >= kPipeSlots) st = hip_check(hipStreamWaitEvent(stream_bp, scl_done[s], 0), "stream wait");
-        if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], stream_bp, g_pipe_bp_wgs.load());
+        if (st == POLAR_OK) st = enqueue_bp_part(code, llr[j], B, p, w[s], info_hat[j], stream_bp, g_pipe_bp_wgs.load());
         if (st == POLAR_OK) st = hip_check(hipEventRecord(bp_done[s], stream_bp), "event record");
         if (st == POLAR_OK) st = hip_check(hipStreamWaitEvent(stream_scl, bp_done[s], 0), "stream wait");
         if (st == POLAR_OK)

@@ -85,9 +85,10 @@ polar_status hip_check(hipError_t e, const char* what);
 // wgs_per_cu > 0: at most that many BP workgroups per CU at a time (a
 // persistent grid), where such a kernel exists (min-sum, unweighted or
 // per-stage weights); otherwise one workgroup per frame group
+// info_out (or null): [B][K] information bits of the frames whose verdict is ok
 polar_status launch_bp(const polar_code* code, const float* llr, int64_t B, const bp_params* p,
                        uint8_t* u_hat, float* llr_u, int32_t* iters, uint8_t* ok,
-                       hipStream_t stream, int wgs_per_cu = 0);
+                       hipStream_t stream, int wgs_per_cu = 0, uint8_t* info_out = nullptr);
 polar_status launch_bp_save(const polar_code* code, const float* llr, int64_t B, int T, float llr_max,
                             const float* W, int variant, uint8_t* u_hat, float* llr_u, uint8_t* ok, float* saved,
                             hipStream_t stream);
