@@ -53,10 +53,11 @@ VALU_PEAK_GOPS = CU * LANES * CLOCK_GHZ  # one 32-bit VALU operation per lane pe
 POLY24 = 0x864CFB
 
 # HBM bytes per 65536-frame launch of the weighted BP kernel (one weight per
-# stage column), from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size; valid only
-# for the kernel sources they were measured on (hash of the files below)
-BP_TRAFFIC = {"bytes": 349621453, "frames": 65536, "src_sha256_16": "5a64bcb9261ce622"}
+# stage column) as the per-kernel timing loop runs it (u_hat written), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a device copy of known size;
+# valid only for the kernel sources they were measured on (hash of the files
+# below)
+BP_TRAFFIC = {"bytes": 349389669, "frames": 65536, "src_sha256_16": "58245a7e0d391693"}
 BP_SOURCES = ("paper_1609_09358_amd/csrc/bp.hip", "paper_1609_09358_amd/csrc/bp_common.hpp",
               "paper_1609_09358_amd/csrc/bp_geom.hpp")
 
