@@ -227,6 +227,8 @@ def test_scl_frame_subset_scatters_rows():
 # ------------------------------------------------------------------ hybrid
 
 @pytest.mark.parametrize("N,K,c,L,design,ebn0,max_iter", [
+    (64, 24, 8, 4, 2.0, 1.0, 30),
+    (512, 256, 16, 8, 2.5, 1.5, 40),
     (256, 128, 8, 4, 2.5, 1.5, 40),
     (1024, 512, 16, 8, 2.5, 1.5, 200),
     (1024, 512, 24, 32, 2.5, 1.5, 20),
