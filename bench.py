@@ -317,6 +317,7 @@ def main():
     extra["latency"] = latency_study(code, learned, T, W)
     extra["c5_other_points"] = c5_points(code, learned_pipe, plain_pipe, learned, plain, B)
     extra["c2_rules"] = c2_rules(args.frames, max(3, args.steps // 4))
+    extra["c2_sweep"] = c2_sweep(args.frames, max(3, args.steps // 4))
     extra["paper_operating_point"] = paper_operating_point()
 
     cpu = None
@@ -500,6 +501,52 @@ def c2_rules(B, steps, ebn0=2.5):
             "fer": float((out["info"] != info).any(dim=1).float().mean()),
         }
     return res
+
+
+def c2_sweep(B, steps, ebn0s=(1.5, 2.0, 2.5, 3.0), fer_frames=100_000):
+    """The plain hybrid of its configuration (N=1024 K=512 CRC-16, GA at
+    2.5 dB, min-sum BP i_max=200, CA-SCL L=8) over Eb/N0: single-stream and
+    pipelined throughput on one resident batch, BP failure rate, mean
+    iterations, and FER on 1e5 fresh frames per point."""
+    import torch
+
+    from paper_1609_09358_amd import binding as PB
+    from paper_1609_09358_amd import train_wbp as TW
+
+    code = PB.PolarCode(1024, 512, 16, 0, 2.5)
+    dec = PB.HybridDecoder(code, max_iter=200, L=8)
+    pipe = PB.HybridPipeline(code, max_iter=200, L=8)
+    rows = []
+    for e in ebn0s:
+        gen = TW.Trainer(code, 1, 16, seed=int(100 * e) + 2)
+        _, _, llr = gen.frames(B, ebn0=e)
+        out = dec(llr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dec(llr, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        outs = [{"info": torch.empty((B, code.K), dtype=torch.uint8, device="cuda")} for _ in range(2)]
+        pipe([llr] * 2, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pipe([llr] * steps, outs=[outs[i % 2] for i in range(steps)])
+        torch.cuda.synchronize()
+        dtp = (time.perf_counter() - t0) / steps
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        nf = err = 0
+        while nf < fer_frames:
+            b = min(B, fer_frames - nf)
+            inf_f, _, llr_f = gen.frames(b, ebn0=e)
+            err += int((dec(llr_f, stats=st)["info"] != inf_f).any(dim=1).sum())
+            nf += b
+        s = st.cpu().numpy()
+        rows.append({"ebn0_db": e, "Gbps": round(B * code.K / dt / 1e9, 4),
+                     "pipelined_Gbps": round(B * code.K / dtp / 1e9, 4),
+                     "bp_fail_rate": float(s[2]) / float(s[0]), "mean_bp_iterations": float(s[3]) / float(s[0]),
+                     "fer": err / nf, "fer_frames": nf})
+    return rows
 
 
 def paper_operating_point(B=16384, reps=3, da_bits=1024):
