@@ -6,6 +6,7 @@ closed forms, noiseless inputs, symmetry of the code, central finite
 differences, and the decoders' known relations (SCL with L = 1 is SC).
 """
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -133,6 +134,47 @@ def test_bp_stop_rules():
             b = g["u_hat"][f][free]
             assert np.array_equal(O.crc(b[:K], c, poly), b[K:])
         assert r["iters"][f] <= 60
+
+
+def _read_n4_golden():
+    g = {"iters": {}, "stop1": {}}
+    path = os.path.join(os.path.dirname(__file__), "golden", "bp_n4_minsum.txt")
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if not line:
+            continue
+        if line[0] == "iter":
+            g["iters"].setdefault(int(line[1]), {})[line[2]] = np.array([float(v) for v in line[3:]])
+        elif line[0] == "stop1":
+            g["stop1"][line[1]] = np.array([int(v) for v in line[2:]])
+        else:
+            g[line[0]] = np.array([float(v) for v in line[1:]])
+    return g
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bp_n4_worked_example(prec):
+    """Messages of two BP iterations on N = 4, worked by hand from the PE
+    equations of Sec. II-B in the paper's sweep order (R over stages 2..n+1,
+    then L over n..1): tests/golden/bp_n4_minsum.txt.  Fixes the schedule, the
+    port mapping, the clipping of a computed sum and the re-encoding stop."""
+    g = _read_n4_golden()
+    fr = g["frozen"].astype(np.uint8)
+    llr = g["llr"].astype(np.float32)
+    for T in (1, 2):
+        r = O.bp_frame(llr, fr, max_iter=T, stop=0, llr_max=float(g["llr_max"][0]), save=True, prec=prec)
+        want = g["iters"][T]
+        sv = r["save"][T - 1]  # [dir][column][node]: R row s+1 / L row s
+        np.testing.assert_array_equal(sv[0][0], want["R1"])
+        np.testing.assert_array_equal(sv[0][1], want["R2"])
+        np.testing.assert_array_equal(sv[1][1], want["L1"])
+        np.testing.assert_array_equal(sv[1][0], want["L0"])
+        np.testing.assert_array_equal(r["llr_u"], want["llr_u"])
+        np.testing.assert_array_equal(r["llr_x"], want["llr_x"])
+    r = O.bp_frame(llr, fr, max_iter=2, stop=1, prec=prec)
+    assert r["iters"] == g["stop1"]["iters"][0]
+    np.testing.assert_array_equal(r["u_hat"], g["stop1"]["u_hat"])
+    assert r["ok"] == g["stop1"]["ok"][0]
 
 
 def test_bp_f32_and_f64_agree():
@@ -450,6 +492,45 @@ def test_wbp_multi_loss_gradient_matches_finite_differences():
         if abs(fd - dW.reshape(-1)[q]) > 1e-6 + 1e-5 * abs(fd):
             bad += 1
     assert bad <= 1, bad
+
+
+def test_wbp_channel_gradient_matches_finite_differences():
+    """d loss / d llr against central differences on the double oracle.  The
+    LLRs are rounded to multiples of 2^-12 and perturbed by +-2^-12, so every
+    perturbed input is an exact float32 (the oracle's input type); a few
+    channel LLRs lie beyond the clipping level, where the loss does not depend
+    on them (the clip at load has derivative 0)."""
+    N, T, K = 16, 3, 8
+    n = 4
+    rng = np.random.default_rng(23)
+    fr = O.ga_frozen(N, K, 0.0, 0.5)
+    info = rng.integers(0, 2, (3, K)).astype(np.uint8)
+    u, x = O.encode_batch(info, K, 0, 0, fr)
+    llr = O.channel_llr(x, rng.standard_normal((3, N)), O.sigma2(0.0, 0.5)).astype(np.float64)
+    llr[0, 3] = 25.0
+    llr[1, 9] = -23.5
+    llr[2, 0] = 20.75
+    # the last node with a wrong-signed LLR beyond the clip: without the clip at
+    # load its adjoint would be -1/24 here (the sums it enters stay unclipped)
+    llr[:, N - 1] = 22.0 * (2.0 * x[:, N - 1] - 1.0)
+    h = 2.0 ** -12
+    llr = (np.round(llr / h) * h).astype(np.float32)
+    W = rng.uniform(0.5, 1.5, (T, 2, n, N))
+    s = 1.0 / (3 * K)
+    _, _, dl = O.wbp_grad(llr, fr, u, T, W, scale=s, want_dllr=True)
+    assert np.all(dl[np.abs(llr) > 20] == 0)
+    bad = 0
+    for f in range(3):
+        for i in range(N):
+            lp = llr[f:f + 1].copy(); lp[0, i] += np.float32(h)
+            lm = llr[f:f + 1].copy(); lm[0, i] -= np.float32(h)
+            assert float(lp[0, i]) - float(llr[f, i]) == h and float(llr[f, i]) - float(lm[0, i]) == h
+            fd = (O.wbp_grad(lp, fr, u[f:f + 1], T, W, scale=s)[0]
+                  - O.wbp_grad(lm, fr, u[f:f + 1], T, W, scale=s)[0]) / (2 * h)
+            if abs(fd - dl[f, i]) > 1e-6 + 1e-4 * abs(fd):
+                bad += 1
+    assert bad <= 1, bad
+    assert np.count_nonzero(dl) >= 30
 
 
 def test_adam_first_step_closed_form():
