@@ -192,7 +192,7 @@ polar_status scl_decode_batch(const polar_code* code, const float* llr, int64_t 
 /* ---------------------------------------------------------------------------
  * Hybrid decoder (Sec. III, Fig. 3): BP with params->max_iter iterations and
  * the params->stop rule on every frame; frames whose verdict is not ok are
- * compacted into a queue on the device ("copy failed CWs to buffer") and
+ * compacted into a queue on the device (the failed-codeword buffer of Fig. 3) and
  * decoded again from their channel LLRs by the CA-SCL decoder with list size
  * L.  No host round trip: the queue length stays on the device.
  * info_hat  dev [B][K]: information bits of the kept result.

@@ -3,7 +3,7 @@
 // The CPU scheduling loop of Fig. 3 becomes a few kernels on one stream with
 // no host round trip: BP on every frame (it writes the information bits of
 // the frames it keeps), compaction of the frames whose BP verdict is not ok
-// into a device queue ("copy failed CWs to buffer"), persistent CA-SCL
+// into a device queue (the failed-codeword buffer of Fig. 3), persistent CA-SCL
 // workgroups that read the queue length on the device, a pass over the flags
 // and statistics, and a merge of the list-decoded frames' information bits.
 #include <atomic>
