@@ -200,11 +200,23 @@ polar_status scl_decode_batch(const polar_code* code, const float* llr, int64_t 
  * stats     dev int64 [8] or NULL, accumulated (not cleared):
  *           [0] frames, [1] BP ok, [2] SCL frames, [3] BP iterations summed,
  *           [4] SCL frames whose CRC failed, [5..7] reserved (0).
+ * Graphs: the kernels of a call are fixed by (device, code, B, params, L,
+ * the buffer pointers, the list decoder's tuning settings).  The first call
+ * with such a combination launches them directly; the second captures them
+ * into one hipGraph and every later call with the same combination replays
+ * it on `stream` (the kernels read the buffers, including the weights, when
+ * they run, so their contents may change between calls).  The library keeps
+ * the graphs of the 8 most recently used combinations.  Calls on a stream
+ * that is being captured launch directly.  polar_set_hybrid_graphs(0) turns
+ * the replay off (process-wide), 1 (the default) on.
  * ------------------------------------------------------------------------- */
 polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64_t B,
                                  const bp_params* params, int32_t L, uint8_t* info_hat,
                                  uint8_t* used_scl, int64_t* stats, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
+
+polar_status polar_set_hybrid_graphs(int32_t mode);
+int32_t polar_get_hybrid_graphs(void);
 
 /* ---------------------------------------------------------------------------
  * Pipelined hybrid over a sequence of batches: the asynchronous BP / SCL

@@ -81,6 +81,10 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = C.c_int
+        L.polar_set_hybrid_graphs.argtypes = [i32]
+        L.polar_set_hybrid_graphs.restype = C.c_int
+        L.polar_get_hybrid_graphs.argtypes = []
+        L.polar_get_hybrid_graphs.restype = i32
         L.polar_get_scl_ranking.argtypes = []
         L.polar_get_scl_ranking.restype = i32
         L.polar_get_pipeline_bp_occupancy.argtypes = []
@@ -252,6 +256,16 @@ def polar_set_scl_ranking(mode: int):
 
 def polar_get_scl_ranking() -> int:
     return int(lib().polar_get_scl_ranking())
+
+
+def polar_set_hybrid_graphs(mode: int):
+    """hybrid_decode_batch: 1 (default) replay a captured graph from the second
+    call with the same arguments on, 0 launch the kernels directly."""
+    _check(lib().polar_set_hybrid_graphs(int(mode)))
+
+
+def polar_get_hybrid_graphs() -> int:
+    return int(lib().polar_get_hybrid_graphs())
 
 
 def polar_set_pipeline_bp_occupancy(wgs_per_cu: int):
@@ -513,7 +527,8 @@ class WeightedBPLoss(torch.autograd.Function):
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
             "polar_code_decision_aided",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
-            "hybrid_decode_batch", "polar_workspace_size", "wbp_forward", "wbp_bce",
+            "hybrid_decode_batch", "polar_set_hybrid_graphs",
+            "polar_get_hybrid_graphs", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
             "polar_get_pipeline_bp_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",

@@ -9,6 +9,7 @@
 // variable-node side to 2m; the first step decides the most significant index
 // bit.  phi uses the two-piece approximation of Chung et al.; below the point
 // where that approximation exceeds 1 the check side gives 0.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -239,7 +240,9 @@ polar_status polar_build_code(const polar_code_desc* d, polar_code** out) {
             }
     }
 
+    static std::atomic<uint64_t> next_serial{1};
     polar_code* code = new polar_code();
+    code->serial = next_serial.fetch_add(1);
     code->N = N;
     code->n = n;
     code->K = K;

@@ -7,6 +7,8 @@
 // workgroups that read the queue length on the device, a pass over the flags
 // and statistics, and a merge of the list-decoded frames' information bits.
 #include <atomic>
+#include <cstring>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -226,6 +228,78 @@ extern "C" polar_status polar_pipeline_workspace_size(const polar_code* code, in
     return ok_status();
 }
 
+namespace {
+
+// Captured graphs of hybrid_decode_batch.  A call's work is fully determined
+// by this key (the kernels read the weights, LLRs and tables through the
+// pointers, so their contents may change between calls); the first call with
+// a key runs the kernels directly, the second captures them into a graph on a
+// library stream and every later one replays that graph on the caller's
+// stream.  Codes carry a serial number, so a code freed and another built at
+// the same address never match.
+struct HybridKey {
+    int dev;
+    const polar_code* code;
+    uint64_t serial;
+    const float* llr;
+    int64_t B;
+    bp_params p;
+    int32_t L;
+    uint8_t* info_hat;
+    uint8_t* used_scl;
+    int64_t* stats;
+    void* ws;
+    int64_t lds_budget;
+    int32_t ranking;
+    bool operator==(const HybridKey& o) const {
+        return dev == o.dev && code == o.code && serial == o.serial && llr == o.llr && B == o.B &&
+               p.max_iter == o.p.max_iter && p.stop == o.p.stop && p.llr_max == o.p.llr_max &&
+               p.rule == o.p.rule && p.weights == o.p.weights && p.weight_iters == o.p.weight_iters &&
+               p.variant == o.p.variant && p.weight_layout == o.p.weight_layout && L == o.L &&
+               info_hat == o.info_hat && used_scl == o.used_scl && stats == o.stats && ws == o.ws &&
+               lds_budget == o.lds_budget && ranking == o.ranking;
+    }
+};
+
+struct HybridGraph {
+    HybridKey key;
+    int calls = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;  // last use, for replacement
+};
+
+constexpr int kGraphSlots = 8;
+std::mutex g_graph_mu;
+HybridGraph g_graphs[kGraphSlots];
+uint64_t g_graph_clock = 0;
+std::atomic<int> g_graph_mode{1};
+
+// per-device stream on which hybrid graphs are captured
+polar_status capture_stream(int dev, hipStream_t* out) {
+    constexpr int kMaxDev = 64;
+    static hipStream_t streams[kMaxDev] = {};
+    if (dev < 0 || dev >= kMaxDev) return set_error(POLAR_ERR_UNSUPPORTED, "device index out of range");
+    if (!streams[dev]) {
+        polar_status st = hip_check(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "stream create");
+        if (st != POLAR_OK) return st;
+    }
+    *out = streams[dev];
+    return POLAR_OK;
+}
+
+polar_status enqueue_hybrid(const polar_code* code, const SclPlan& plan, const float* llr, int64_t B,
+                            const bp_params* p, int32_t L, uint8_t* info_hat, uint8_t* used_scl, int64_t* stats,
+                            void* ws, hipStream_t stream) {
+    HybridWs w;
+    carve(code, B, plan, ws, &w, 1);
+    polar_status st = enqueue_bp_part(code, llr, B, p, w, info_hat, stream);
+    if (st != POLAR_OK) return st;
+    return enqueue_scl_part(code, plan, llr, B, L, w, info_hat, used_scl, stats, stream);
+}
+
+}  // namespace
+
 extern "C" polar_status hybrid_decode_batch(const polar_code* code, const float* llr, int64_t B,
                                             const bp_params* p, int32_t L, uint8_t* info_hat, uint8_t* used_scl,
                                             int64_t* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
@@ -239,12 +313,80 @@ extern "C" polar_status hybrid_decode_batch(const polar_code* code, const float*
     const size_t need = carve(code, B, plan, nullptr, nullptr, 1);
     if (!ws || ws_bytes < need) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_batch: workspace too small");
     if (B == 0) return ok_status();
-    HybridWs w;
-    carve(code, B, plan, ws, &w, 1);
-    if ((st = enqueue_bp_part(code, llr, B, p, w, info_hat, stream)) != POLAR_OK) return st;
-    if ((st = enqueue_scl_part(code, plan, llr, B, L, w, info_hat, used_scl, stats, stream)) != POLAR_OK) return st;
+    // work enqueued on a stream the caller is capturing is recorded there
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if ((st = hip_check(hipStreamIsCapturing(stream, &cap), "stream capture query")) != POLAR_OK) return st;
+    if (g_graph_mode.load() == 0 || cap != hipStreamCaptureStatusNone) {
+        st = enqueue_hybrid(code, plan, llr, B, p, L, info_hat, used_scl, stats, ws, stream);
+        return st == POLAR_OK ? ok_status() : st;
+    }
+    HybridKey key;
+    std::memset(&key, 0, sizeof(key));
+    if ((st = hip_check(hipGetDevice(&key.dev), "get device")) != POLAR_OK) return st;
+    key.code = code;
+    key.serial = code->serial;
+    key.llr = llr;
+    key.B = B;
+    key.p = *p;
+    key.L = L;
+    key.info_hat = info_hat;
+    key.used_scl = used_scl;
+    key.stats = stats;
+    key.ws = ws;
+    key.lds_budget = polar_get_scl_lds_budget();
+    key.ranking = polar_get_scl_ranking();
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    HybridGraph* slot = nullptr;
+    for (HybridGraph& g : g_graphs)
+        if (g.calls > 0 && g.key == key) slot = &g;
+    if (!slot) {
+        // first call with this key: run directly and remember the key in the
+        // least recently used slot
+        HybridGraph* victim = &g_graphs[0];
+        for (HybridGraph& g : g_graphs)
+            if (g.used < victim->used) victim = &g;
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        if (victim->graph) (void)hipGraphDestroy(victim->graph);
+        *victim = HybridGraph();
+        victim->key = key;
+        victim->calls = 1;
+        victim->used = ++g_graph_clock;
+        st = enqueue_hybrid(code, plan, llr, B, p, L, info_hat, used_scl, stats, ws, stream);
+        return st == POLAR_OK ? ok_status() : st;
+    }
+    slot->used = ++g_graph_clock;
+    if (!slot->exec) {
+        hipStream_t cs = nullptr;
+        if ((st = capture_stream(key.dev, &cs)) != POLAR_OK) return st;
+        if ((st = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) != POLAR_OK)
+            return st;
+        polar_status se = enqueue_hybrid(code, plan, llr, B, p, L, info_hat, used_scl, stats, ws, cs);
+        hipGraph_t g = nullptr;
+        st = hip_check(hipStreamEndCapture(cs, &g), "end capture");
+        if (se != POLAR_OK || st != POLAR_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return se != POLAR_OK ? se : st;
+        }
+        hipGraphExec_t ex = nullptr;
+        if ((st = hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate")) != POLAR_OK) {
+            (void)hipGraphDestroy(g);
+            return st;
+        }
+        slot->graph = g;
+        slot->exec = ex;
+    }
+    ++slot->calls;
+    st = hip_check(hipGraphLaunch(slot->exec, stream), "graph launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
+extern "C" polar_status polar_set_hybrid_graphs(int32_t mode) {
+    if (mode != 0 && mode != 1) return set_error(POLAR_ERR_INVALID_ARG, "polar_set_hybrid_graphs: mode must be 0 or 1");
+    g_graph_mode.store(mode);
     return ok_status();
 }
+
+extern "C" int32_t polar_get_hybrid_graphs(void) { return g_graph_mode.load(); }
 
 extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, const float* const* llr,
                                                 int64_t B, const bp_params* p, int32_t L, uint8_t* const* info_hat,

@@ -47,6 +47,7 @@ struct polar_code {
     int32_t N, n, K, c, k;
     uint32_t poly;
     int device;
+    uint64_t serial;                // distinct for every code built in the process
     std::vector<uint8_t> frozen;    // host [N]
     std::vector<int16_t> info_pos;  // host [k]
     std::vector<uint8_t> da;        // host [N], decision-aided positions

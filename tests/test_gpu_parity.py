@@ -124,24 +124,74 @@ def test_bp_exact_rule_soft_output_vs_f64_oracle(N, K, c, iters):
     assert err.max() <= 1e-4, err.max()
 
 
-def test_bp_exact_rule_full_runs_vs_f64_oracle():
-    """Whole decodes (re-encoding stop, up to 40 iterations): the device's
-    single-precision transcendentals differ from the host's double ones in the
-    last bits, so a frame may stop an iteration earlier or later; verdicts and
-    decisions agree on almost every frame, and whenever both stop with ok the
-    decisions are identical."""
-    N, K, c, B = 256, 128, 8, 300
-    code, info, u, x, llr = frames(N, K, c, 2.0, 2.0, B, seed=77)
-    out = PB.bp_decode_batch(code, dev(llr), max_iter=40, stop=1, rule=1)
-    ref = O.bp_batch(llr, code.frozen, c, POLY[c], max_iter=40, stop=1, rule=1, prec="f64")
-    ok, ok_r = host(out["ok"]).astype(bool), ref["ok"].astype(bool)
-    uh = host(out["u_hat"])
-    assert np.mean(ok == ok_r) >= 0.97
-    both = ok & ok_r
-    assert both.sum() > B // 2
-    assert np.array_equal(uh[both], ref["u_hat"][both])
-    it, it_r = host(out["iters"]), ref["iters"]
-    assert np.mean(np.abs(it.astype(int) - it_r) <= 1) >= 0.97
+def exact_rule_flags(llr, frozen, c, max_iter):
+    """Frames whose exact-rule BP outcome (iteration count, verdict, and the
+    decisions of a frame that stopped before max_iter) depends on rounding: it
+    differs between the oracle's double and float builds, or in the double
+    build when every channel LLR is scaled by 1 +- 2^-20.  The device evaluates
+    the exact rule with single-precision transcendentals, whose last bits
+    differ from the host's, so only these near-tie frames may decode
+    differently.  Returns (flags, double-build result)."""
+    base = O.bp_batch(llr, frozen, c, POLY[c], max_iter=max_iter, stop=1, rule=1, prec="f64")
+    others = [O.bp_batch(llr, frozen, c, POLY[c], max_iter=max_iter, stop=1, rule=1, prec="f32")]
+    for s in (1.0 + 2.0 ** -20, 1.0 - 2.0 ** -20):
+        others.append(O.bp_batch((llr.astype(np.float64) * s).astype(np.float32), frozen, c, POLY[c],
+                                 max_iter=max_iter, stop=1, rule=1, prec="f64"))
+    flag = np.zeros(len(llr), bool)
+    stopped = base["iters"] < max_iter
+    for r in others:
+        flag |= (r["iters"] != base["iters"]) | (r["ok"] != base["ok"])
+        flag |= stopped & np.any(r["u_hat"] != base["u_hat"], axis=1)
+    return flag, base
+
+
+@pytest.mark.parametrize("N,K,c,ebn0,max_iter", [(256, 128, 8, 2.0, 40), (1024, 512, 16, 2.0, 50)])
+def test_bp_exact_rule_full_runs_vs_f64_oracle(N, K, c, ebn0, max_iter):
+    """Whole decodes with the exact rule (re-encoding stop): iteration counts
+    and verdicts equal the double oracle's on every frame that is not flagged
+    as a near tie (see exact_rule_flags), and so do the decisions of every such
+    frame that stopped.  A frame that runs all max_iter iterations without
+    stopping ends in a state where rounding differences have been amplified
+    over many iterations; its last decisions are not compared (the hybrid
+    hands it to the list decoder).  The flagged frames stay a small minority."""
+    B = 120 if N == 256 else 48
+    code, info, u, x, llr = frames(N, K, c, 2.0, ebn0, B, seed=77 + N)
+    out = PB.bp_decode_batch(code, dev(llr), max_iter=max_iter, stop=1, rule=1)
+    flag, ref = exact_rule_flags(llr, code.frozen, c, max_iter)
+    keep = ~flag
+    it, ok, uh = host(out["iters"]), host(out["ok"]), host(out["u_hat"])
+    stopped = keep & (ref["iters"] < max_iter)
+    diff = np.where(keep & np.any(uh != ref["u_hat"], axis=1))[0]
+    print(f"exact rule N={N}: {int(flag.sum())} of {B} frames flagged as near ties; "
+          f"{int(stopped.sum())} unflagged frames stopped; decisions differ on frames {diff.tolist()} "
+          f"(iterations {ref['iters'][diff].tolist()})")
+    assert flag.mean() <= 0.15
+    assert np.array_equal(it[keep], ref["iters"][keep])
+    assert np.array_equal(ok[keep], ref["ok"][keep])
+    assert np.array_equal(uh[stopped], ref["u_hat"][stopped])
+    assert stopped.sum() > B // 2
+    assert 0 < ref["ok"][keep].sum() < keep.sum()
+
+
+@pytest.mark.parametrize("N,K,c,L,ebn0,max_iter,n_da,B", [(1024, 512, 16, 8, 1.75, 50, 0, 40),
+                                                          (4096, 2048, 16, 32, 1.1, 50, 1024, 8)])
+def test_exact_rule_hybrid_vs_oracle(N, K, c, L, ebn0, max_iter, n_da, B):
+    """The hybrid with the paper's exact BP rule (Sec. II-B) and the paper's own
+    operating point (N = 4096, R = 1/2, i_max = 50, L = 32, decision aiding):
+    used_scl and the information bits equal the oracle's hybrid with the same
+    rule on every frame whose BP outcome is not flagged as a near tie."""
+    code0, info, u, x, llr = frames(N, K, c, 2.5, ebn0, B, seed=500 + N)
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=n_da)
+    da = code.decision_aided if n_da else None
+    flag, _ = exact_rule_flags(llr, code.frozen, c, max_iter)
+    keep = ~flag
+    ref = O.hybrid_batch(llr, code.frozen, K, c, POLY[c], max_iter, L, prec="f32", da=da, rule=1)
+    out = PB.HybridDecoder(code, max_iter=max_iter, L=L, rule=1)(dev(llr))
+    print(f"exact-rule hybrid N={N}: {int(flag.sum())} of {B} frames flagged")
+    assert flag.mean() <= 0.2
+    assert np.array_equal(host(out["used_scl"])[keep], ref["used_scl"][keep])
+    assert np.array_equal(host(out["info"])[keep], ref["info"][keep])
+    assert 0 < ref["used_scl"][keep].sum() < keep.sum()
 
 
 @pytest.mark.parametrize("iters", [8, 30])
@@ -187,6 +237,25 @@ def test_scl_bit_exact_vs_f32_oracle(N, K, c, L):
     B = 13 if N >= 1024 else 24
     code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, B, seed=N + L)
     ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32")
+    out = PB.scl_decode_batch(code, dev(llr), L)
+    assert np.array_equal(host(out["crc_ok"]), ref["crc_ok"])
+    assert np.array_equal(host(out["pm"]), ref["pm"].astype(np.float32))
+    assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
+
+
+@pytest.mark.parametrize("n_da", [0, 1024])
+def test_scl_n4096_list32_bit_exact_vs_f32_oracle(n_da):
+    """The paper's operating point for the list decoder (Sec. IV): N = 4096,
+    R = 1/2 (CRC-16), L = 32, whose path memory lives in the global slice;
+    plain CA-SCL and with 1024 decision-aided positions (Sec. II-A)."""
+    N, K, c, L, B = 4096, 2048, 16, 32, 4
+    code0, info, u, x, llr = frames(N, K, c, 2.5, 1.25, B, seed=4096 + n_da)
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=n_da)
+    da = None
+    if n_da:
+        da = O.decision_aided_mask(N, code.frozen, n_da, 2.5, K / N)
+        assert np.array_equal(code.decision_aided, da)
+    ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32", da=da)
     out = PB.scl_decode_batch(code, dev(llr), L)
     assert np.array_equal(host(out["crc_ok"]), ref["crc_ok"])
     assert np.array_equal(host(out["pm"]), ref["pm"].astype(np.float32))
@@ -270,6 +339,46 @@ def test_hybrid_full_size_sampled():
     assert np.array_equal(used[pick], ref["used_scl"])
     fer = np.mean(np.any(info_hat != info, axis=1))
     assert fer < 0.05
+
+
+def test_hybrid_graph_replays_equal_direct_launches():
+    """hybrid_decode_batch replays one captured graph from the second call with
+    the same arguments on.  Replays with new contents in the same input buffer
+    (learned weights updated in place too), with other eager work and
+    synchronisations between them, each equal the direct launches on the same
+    input; the statistics accumulate per call."""
+    N, K, c, L, T, B = 1024, 512, 24, 32, 20, 3000
+    code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=320)
+    batches = [frames(N, K, c, 2.5, e, B, seed=60 + j)[4] for j, e in enumerate((2.0, 1.75, 2.5, 2.0))]
+    W = torch.full((T, 2, 10), 0.94, device="cuda")
+    dec = PB.HybridDecoder(code, max_iter=T, L=L, weights=W)
+    llr = torch.empty((B, N), dtype=torch.float32, device="cuda")
+    out = dict(info=torch.empty((B, K), dtype=torch.uint8, device="cuda"),
+               used_scl=torch.empty(B, dtype=torch.uint8, device="cuda"))
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    assert PB.polar_get_hybrid_graphs() == 1
+    total = np.zeros(8, np.int64)
+    for j, b in enumerate(batches):
+        w = 0.94 if j < 2 else 0.9
+        W.fill_(w)
+        llr.copy_(dev(b))
+        dec(llr, out=out, stats=stats)  # direct (j = 0), captured (j = 1), replayed (j >= 2)
+        got_info, got_used = host(out["info"]).copy(), host(out["used_scl"]).copy()
+        got_stats = host(stats).copy()
+        # eager reference on separate buffers, graphs off
+        PB.polar_set_hybrid_graphs(0)
+        try:
+            st1 = torch.zeros(8, dtype=torch.int64, device="cuda")
+            ref = PB.HybridDecoder(code, max_iter=T, L=L, weights=W)(dev(b), stats=st1)
+            PB.bp_decode_batch(code, dev(b), max_iter=5)  # unrelated eager work
+            ref_info, ref_used, ref_st = host(ref["info"]), host(ref["used_scl"]), host(st1)
+        finally:
+            PB.polar_set_hybrid_graphs(1)
+        assert np.array_equal(got_info, ref_info), j
+        assert np.array_equal(got_used, ref_used), j
+        total += ref_st
+        assert np.array_equal(got_stats, total), j
+        assert 0 < ref_used.sum() < B
 
 
 # ------------------------------------------------------------------ pipelined hybrid (two streams)

@@ -205,3 +205,32 @@ def test_per_stage_weights_equal_expanded_per_node_weights(N, K, c, T, variant, 
     ha = PB.HybridDecoder(code, max_iter=T, L=8, weights=Ws)(dev(llr))
     hb = PB.HybridDecoder(code, max_iter=T, L=8, weights=Wn)(dev(llr))
     assert torch.equal(ha["info"], hb["info"])
+
+
+@pytest.mark.parametrize("layout,lo,hi", [("node", 0.75, 1.05), ("column", 0.75, 1.0), ("column", 0.7, 1.25)])
+@pytest.mark.parametrize("stop", [0, 1])
+@pytest.mark.parametrize("variant", [0, 2])
+def test_weighted_bp_decode_vs_f32_oracle(layout, lo, hi, stop, variant):
+    """bp_decode_batch with learned weights (one per node, or one per stage
+    column) at N = 1024, T = 20 -- the benchmark's decoder when the weights are
+    per column within [0, 1], where the kernel leaves out the clip that cannot
+    act -- against the oracle's float build: soft outputs LLR(u), iteration
+    counts, verdicts and decisions bit for bit."""
+    N, K, c, T, B = 1024, 512, 24, 20, 24
+    n = 10
+    code, u, llr = frames(N, K, c, 2.0, B, seed=900 + int(10 * hi) + stop)
+    rng = np.random.default_rng(int(100 * lo) + stop)
+    shape = (T, 2, n, N) if layout == "node" else (T, 2, n)
+    w = rng.uniform(lo, hi, shape).astype(np.float32)
+    if hi == 1.0:
+        w.reshape(-1)[:3] = 1.0
+    Wn = w if layout == "node" else np.repeat(w[..., None], N, axis=3)
+    out = PB.bp_decode_batch(code, dev(llr), max_iter=T, stop=stop, weights=dev(w), variant=variant, soft=True)
+    ref = O.bp_batch(llr, code.frozen, c, POLY[c], max_iter=T, stop=stop, W=Wn.astype(np.float64), prec="f32",
+                     soft=True)
+    assert np.array_equal(host(out["iters"]), ref["iters"])
+    assert np.array_equal(host(out["ok"]), ref["ok"])
+    assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
+    assert np.array_equal(host(out["llr_u"]), ref["llr_u"].astype(np.float32))
+    if stop == 1:
+        assert 0 < ref["ok"].sum() < B
