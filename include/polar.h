@@ -219,6 +219,28 @@ polar_status polar_set_hybrid_graphs(int32_t mode);
 int32_t polar_get_hybrid_graphs(void);
 
 /* ---------------------------------------------------------------------------
+ * hybrid_decode_batch for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same decode, arguments and results, without a workspace
+ * argument.  The workspace lives in a fixed 64 MiB array of device memory
+ * that the library holds on each device it runs on until the process ends;
+ * the call allocates nothing.  The batch state takes about B * (N + 10)
+ * bytes (plus alignment) and the list decoder's global slice at least one
+ * workgroup's share (L * N * 4 + k * L bytes when its state does not fit in
+ * LDS); a batch that does not fit returns POLAR_ERR_INVALID_ARG before
+ * anything is enqueued.  At N = 1024, L = 32 up to about 64000 frames fit.
+ * With less room than hybrid_decode_batch would take, the list decoder runs
+ * fewer persistent workgroups (same results, lower throughput when many
+ * frames fail BP).  All calls on one device share that array: calls that can
+ * overlap on a device (other streams, other threads) race and must be
+ * serialised by the caller; a call does not depend on what an earlier one
+ * left there.
+ * ------------------------------------------------------------------------- */
+polar_status hybrid_decode_batch_static(const polar_code* code, const float* llr, int64_t B,
+                                        const bp_params* params, int32_t L, uint8_t* info_hat,
+                                        uint8_t* used_scl, int64_t* stats, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Pipelined hybrid over a sequence of batches: the asynchronous BP / SCL
  * scheduling of Sec. III (Fig. 3) on two streams.  For batch j, BP and the
  * compaction of its failed frames run on stream_bp; its CA-SCL and the merge

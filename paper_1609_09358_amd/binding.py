@@ -62,6 +62,7 @@ def lib():
             "polar_bp_variants": [i32, C.POINTER(i32), i32, C.POINTER(i32)],
             "scl_decode_batch": [vp, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
             "hybrid_decode_batch": [vp, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp],
+            "hybrid_decode_batch_static": [vp, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp],
             "polar_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
             "wbp_forward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, vp, vp],
             "wbp_bce": [vp, vp, vp, i64, C.c_double, vp, vp, vp],
@@ -333,6 +334,26 @@ def hybrid_decode_batch(code: PolarCode, llr: torch.Tensor, params: bp_params, L
     return out
 
 
+def hybrid_decode_batch_static(code: PolarCode, llr: torch.Tensor, params: bp_params, L: int, out=None,
+                               stats=None):
+    """hybrid_decode_batch without a workspace: the library's fixed device
+    scratch is used (no allocation inside the call; calls on one device must
+    not overlap)."""
+    B = llr.shape[0]
+    _dev(llr, torch.float32, (B, code.N), "llr")
+    dev = llr.device
+    if out is None:
+        out = dict(info=torch.empty((B, code.K), dtype=torch.uint8, device=dev),
+                   used_scl=torch.empty(B, dtype=torch.uint8, device=dev))
+    _dev(out["info"], torch.uint8, (B, code.K), "info")
+    _dev(out.get("used_scl"), torch.uint8, (B,), "used_scl")
+    if stats is not None:
+        _dev(stats, torch.int64, (8,), "stats")
+    _check(lib().hybrid_decode_batch_static(code.handle, _ptr(llr), B, C.byref(params), L, _ptr(out["info"]),
+                                            _ptr(out.get("used_scl")), _ptr(stats), _stream()))
+    return out
+
+
 def polar_pipeline_workspace_size(code: PolarCode, B, L, params: bp_params) -> int:
     s = C.c_size_t()
     _check(lib().polar_pipeline_workspace_size(code.handle, B, L, C.byref(params), C.byref(s)))
@@ -527,7 +548,7 @@ class WeightedBPLoss(torch.autograd.Function):
 EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "polar_free_code", "polar_code_params", "polar_code_frozen",
             "polar_code_decision_aided",
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
-            "hybrid_decode_batch", "polar_set_hybrid_graphs",
+            "hybrid_decode_batch", "hybrid_decode_batch_static", "polar_set_hybrid_graphs",
             "polar_get_hybrid_graphs", "polar_workspace_size", "wbp_forward", "wbp_bce",
             "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",

@@ -12,6 +12,14 @@
 
 #include "internal.hpp"
 
+// Device memory of hybrid_decode_batch_static: the per-batch state and the
+// list decoder's global slice of one call.  Each device the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device (the name
+// itself is a host-side stand-in).
+static constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace polarhip {
 namespace {
 
@@ -387,6 +395,62 @@ extern "C" polar_status polar_set_hybrid_graphs(int32_t mode) {
 }
 
 extern "C" int32_t polar_get_hybrid_graphs(void) { return g_graph_mode.load(); }
+
+// device address of `scratch` on the current device, looked up once per device
+static polar_status static_scratch(void** out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDev] = {};
+    int dev = 0;
+    polar_status st = hip_check(hipGetDevice(&dev), "get device");
+    if (st != POLAR_OK) return st;
+    if (dev < 0 || dev >= kMaxDev) return set_error(POLAR_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (st != POLAR_OK) return st;
+        if (!p) return set_error(POLAR_ERR_DEVICE, "scratch symbol address is null");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return POLAR_OK;
+}
+
+extern "C" polar_status hybrid_decode_batch_static(const polar_code* code, const float* llr, int64_t B,
+                                                   const bp_params* p, int32_t L, uint8_t* info_hat,
+                                                   uint8_t* used_scl, int64_t* stats, hipStream_t stream) {
+    if (!code || !p) return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_batch_static: null code or params");
+    if (B < 0 || B > (int64_t)INT32_MAX)
+        return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_batch_static: bad batch size");
+    if (B > 0 && (!llr || !info_hat))
+        return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_batch_static: null buffer");
+    polar_status st = check_bp_params(code, p);
+    if (st != POLAR_OK) return st;
+    SclPlan plan;
+    if ((st = scl_plan(code, L, B > 0 ? B : 1, &plan)) != POLAR_OK) return st;
+    // the per-batch state first; the list decoder then runs as many
+    // persistent workgroups as global slices fit in the rest (at least one)
+    const size_t batch = carve_batch(code, B, 0, nullptr, nullptr);
+    if (batch + plan.glob_per_wg > kStaticScratchBytes)
+        return set_error(POLAR_ERR_INVALID_ARG,
+                         "hybrid_decode_batch_static: batch needs " + std::to_string(batch + plan.glob_per_wg) +
+                             " bytes of scratch, the maximum is " + std::to_string(kStaticScratchBytes));
+    if (plan.glob_per_wg) {
+        const size_t fit = (kStaticScratchBytes - batch) / plan.glob_per_wg;
+        if ((size_t)plan.grid > fit) plan.grid = (int)fit;
+    }
+    if (carve(code, B, plan, nullptr, nullptr, 1) > kStaticScratchBytes)
+        return set_error(POLAR_ERR_INVALID_ARG, "hybrid_decode_batch_static: batch too large for the scratch");
+    if (B == 0) return ok_status();
+    void* ws = nullptr;
+    if ((st = static_scratch(&ws)) != POLAR_OK) return st;
+    HybridWs w;
+    carve(code, B, plan, ws, &w, 1);
+    if ((st = enqueue_bp_part(code, llr, B, p, w, info_hat, stream)) != POLAR_OK) return st;
+    if ((st = enqueue_scl_part(code, plan, llr, B, L, w, info_hat, used_scl, stats, stream)) != POLAR_OK) return st;
+    return ok_status();
+}
 
 extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t nbatch, const float* const* llr,
                                                 int64_t B, const bp_params* p, int32_t L, uint8_t* const* info_hat,
