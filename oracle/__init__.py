@@ -287,12 +287,17 @@ def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, pre
     return dict(info=info, used_scl=used, iters=it)
 
 
-def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", want_dllr=False, multi=False):
+def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", want_dllr=False, multi=False,
+             kind=None):
     """Loss and gradients of the weighted BP (batch).  Returns (loss, dW[, dllr]).
 
-    The loss is the BCE of LLR(u) after the last iteration, or (multi) the sum
-    of that BCE after every iteration.  scale defaults to 1 / (B * k) (times
-    1 / T for multi): the mean over frames, non-frozen bits (and iterations)."""
+    kind 0 (default): the BCE of LLR(u) after the last iteration; kind 1
+    (or multi=True): the sum of that BCE after every iteration; kind 2: the
+    frame-failure surrogate prod_t (1 - exp(-S_t)), S_t the frame's BCE sum
+    after iteration t.  scale defaults to 1 / (B * k) for kind 0, 1 / (B * k * T)
+    for kind 1 (means over frames, non-frozen bits and iterations) and 1 / B
+    for kind 2 (the mean over frames)."""
+    kind = (1 if multi else 0) if kind is None else int(kind)
     fr = _u8(frozen)
     N = len(fr)
     n = N.bit_length() - 1
@@ -301,12 +306,12 @@ def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", wa
     B = llr.shape[0]
     k = int((fr == 0).sum())
     if scale is None:
-        scale = 1.0 / (B * k * (T if multi else 1))
+        scale = {0: 1.0 / (B * k), 1: 1.0 / (B * k * T), 2: 1.0 / B}[kind]
     W = _f64(W).reshape(T, 2, n, N)
     dW = np.zeros((T, 2, n, N), np.float64)
     dl = np.zeros((B, N), np.float64) if want_dllr else None
     loss = _lib(prec).orc_wbp_grad_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(u_true, _u8p),
-                                         T, llr_max, _p(W, _f64p), scale, int(multi), _p(dW, _f64p),
+                                         T, llr_max, _p(W, _f64p), scale, kind, _p(dW, _f64p),
                                          _p(dl, _f64p))
     if want_dllr:
         return loss, dW, dl

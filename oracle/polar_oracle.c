@@ -681,9 +681,18 @@ void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
 /* ------------------------------------------------------------------------ */
 /* Weighted (learned) min-sum BP: loss and its gradient.                     */
 /* Not in the paper.  Forward: the weighted BP above, T iterations, no early */
-/* stop.  Loss of a frame: sum over the non-frozen i of                       */
-/* softplus((2 u_i - 1) lam_i), lam_i = L[0][i] + R[0][i] after iteration T   */
-/* (binary cross-entropy of P(u_i = 1) = sigmoid(-lam_i)), times `scale`.     */
+/* stop.  Losses of a frame (times `scale`), with lam_{t,i} = L[0][i] +      */
+/* R[0][i] after iteration t and z_{t,i} = (2 u_i - 1) lam_{t,i}:             */
+/*   kind 0: sum over the non-frozen i of softplus(z_{T,i}) (binary           */
+/*           cross-entropy of P(u_i = 1) = sigmoid(-lam_i) after the last     */
+/*           iteration);                                                      */
+/*   kind 1: the same sum after every iteration, summed over t;               */
+/*   kind 2: prod_t (1 - exp(-S_t)), S_t = sum_i softplus(z_{t,i}): with the  */
+/*           bits taken as independent, exp(-S_t) is the probability that    */
+/*           every non-frozen decision after iteration t is right, so the     */
+/*           product is the probability that no iteration gets the whole     */
+/*           frame right -- a smooth stand-in for a BP failure within T       */
+/*           iterations (the frames the hybrid hands to the list decoder).    */
 /* Backward (reverse mode, by hand): iterations T..1; inside one, the L sweep */
 /* is undone first (s = 0..n-1), then the R sweep (s = n-1..0).  Rules:       */
 /*   d clip(p)/dp = 1 if |p| <= LLR_max (inclusive), else 0;                  */
@@ -824,36 +833,68 @@ void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int 
 }
 
 double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* u_true,
-                          int T, double llr_max, const double* W, double scale, int multi,
+                          int T, double llr_max, const double* W, double scale, int kind,
                           double* dW /* [T][2][n][N], accumulated */, double* dllr /* N or NULL */) {
     int n = ilog2(N);
     size_t per = (size_t)2 * n * N;
     uint8_t* uh = (uint8_t*)malloc(N);
     uint8_t ok;
     double* lam = (double*)malloc(sizeof(double) * N);
-    int nl = multi ? T : 1;
+    int nl = kind ? T : 1;
     double* dlam = (double*)calloc((size_t)nl * N, sizeof(double));
-    double* save = multi ? (double*)malloc(sizeof(double) * per * T) : NULL;
+    double* save = kind ? (double*)malloc(sizeof(double) * per * T) : NULL;
     orc_bp_frame(llr, N, frozen, 0, 0, T, 0, llr_max, 0, W, uh, lam, NULL, &ok, save);
-    double loss = 0.0;
+    /* lam_{t,i} of the iterations the loss reads */
+    double* lt = (double*)malloc(sizeof(double) * (size_t)nl * N);
     for (int q = 0; q < nl; q++) {
-        int t = multi ? q : T - 1;
-        for (int i = 0; i < N; i++) {
-            if (frozen[i]) continue;
+        int t = kind ? q : T - 1;
+        for (int i = 0; i < N; i++)
             /* LLR(u_i) after iteration t: L row 0 plus the (zero) prior of a
              * non-frozen position, added in working precision as in BP */
-            double lt = multi ? (double)((real)save[(size_t)t * per + (size_t)n * N + i] + (real)0) : lam[i];
-            double sgn_u = u_true[i] ? 1.0 : -1.0;
-            double z = sgn_u * lt;
-            loss += softplus(z);
-            /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
-            double sig = 1.0 / (1.0 + exp(-z));
-            dlam[(size_t)q * N + i] = (double)(real)(scale * sgn_u * sig);
+            lt[(size_t)q * N + i] = kind ? (double)((real)save[(size_t)t * per + (size_t)n * N + i] + (real)0) : lam[i];
+    }
+    double loss = 0.0;
+    if (kind < 2) {
+        for (int q = 0; q < nl; q++)
+            for (int i = 0; i < N; i++) {
+                if (frozen[i]) continue;
+                double sgn_u = u_true[i] ? 1.0 : -1.0;
+                double z = sgn_u * lt[(size_t)q * N + i];
+                loss += softplus(z);
+                /* d softplus(z)/d lam = sgn_u * sigmoid(z) */
+                double sig = 1.0 / (1.0 + exp(-z));
+                dlam[(size_t)q * N + i] = (double)(real)(scale * sgn_u * sig);
+            }
+    } else {
+        /* S_t, then F = prod_t (1 - e^{-S_t}); dF/dS_t = e^{-S_t} prod_{t' != t} (1 - e^{-S_t'}) */
+        double* S = (double*)calloc((size_t)T, sizeof(double));
+        for (int t = 0; t < T; t++)
+            for (int i = 0; i < N; i++) {
+                if (frozen[i]) continue;
+                double sgn_u = u_true[i] ? 1.0 : -1.0;
+                S[t] += softplus(sgn_u * lt[(size_t)t * N + i]);
+            }
+        double F = 1.0;
+        for (int t = 0; t < T; t++) F *= -expm1(-S[t]);
+        loss = F;
+        for (int t = 0; t < T; t++) {
+            double dS = exp(-S[t]);
+            for (int t2 = 0; t2 < T; t2++)
+                if (t2 != t) dS *= -expm1(-S[t2]);
+            for (int i = 0; i < N; i++) {
+                if (frozen[i]) continue;
+                double sgn_u = u_true[i] ? 1.0 : -1.0;
+                double z = sgn_u * lt[(size_t)t * N + i];
+                double sig = 1.0 / (1.0 + exp(-z));
+                dlam[(size_t)t * N + i] = (double)(real)(scale * dS * sgn_u * sig);
+            }
         }
+        free(S);
     }
     orc_wbp_backward_frame(llr, N, frozen, T, llr_max, W, dlam, nl, dW, dllr);
     free(uh);
     free(lam);
+    free(lt);
     free(dlam);
     free(save);
     return loss * scale;
@@ -868,10 +909,10 @@ void orc_wbp_backward_batch(const float* llr, int64_t B, int N, const uint8_t* f
 
 double orc_wbp_grad_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
                           const uint8_t* u_true, int T, double llr_max, const double* W,
-                          double scale, int multi, double* dW, double* dllr) {
+                          double scale, int kind, double* dW, double* dllr) {
     double loss = 0.0;
     for (int64_t f = 0; f < B; f++)
-        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, multi, dW,
+        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, kind, dW,
                                    dllr ? dllr + f * N : NULL);
     return loss;
 }

@@ -543,3 +543,91 @@ def test_adam_first_step_closed_form():
     v = np.zeros(100)
     O.adam_step(w, g, m, v, 1, lr=1e-3)
     np.testing.assert_allclose(w, 1.0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def _truncated_S(llr, fr, u, W, T):
+    """S_t per frame: the BCE sum over the non-frozen bits of LLR(u) from a
+    separate t-iteration decode (no early stop), t = 1..T."""
+    free = fr == 0
+    S = np.zeros((llr.shape[0], T))
+    for t in range(1, T + 1):
+        lam = O.bp_batch(llr, fr, max_iter=t, stop=0, W=W[:t], soft=True)["llr_u"]
+        z = np.where(u == 1, 1.0, -1.0) * lam
+        S[:, t - 1] = np.logaddexp(0.0, z)[:, free].sum(axis=1)
+    return S
+
+
+def test_wbp_frame_loss_value():
+    """Loss kind 2 is the mean over frames of prod_t (1 - exp(-S_t)), S_t the
+    BCE sum of LLR(u) after iteration t, here taken from separate truncated
+    decodes; frames decoded right early get a loss near 0, frames that stay
+    wrong a loss near 1."""
+    N, K, T = 64, 32, 5
+    n = 6
+    rng = np.random.default_rng(19)
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 0.5, seed=74, B=6)
+    W = rng.uniform(0.6, 1.2, (T, 2, n, N))
+    loss = O.wbp_grad(llr, fr, u, T, W, kind=2)[0]
+    S = _truncated_S(llr, fr, u, W, T)
+    ref = np.mean(np.prod(1.0 - np.exp(-S), axis=1))
+    assert abs(loss - ref) <= 1e-12 * max(1.0, ref)
+    # the loss of one frame is the probability, bits independent, that no
+    # iteration's decisions are all right
+    per = [O.wbp_grad(llr[f:f + 1], fr, u[f:f + 1], T, W, kind=2, scale=1.0)[0] for f in range(6)]
+    assert np.all((np.array(per) >= 0) & (np.array(per) <= 1))
+    # noiseless frames: every iteration right with high probability
+    clean = np.where(x == 0, 8.0, -8.0).astype(np.float32)
+    assert O.wbp_grad(clean, fr, u, T, W, kind=2)[0] < 1e-6
+
+
+def test_wbp_frame_loss_single_iteration_closed_form():
+    """T = 1: 1 - exp(-S) with S the final-iteration BCE sum; its gradient is
+    exp(-S) times the BCE gradient (chain rule through the outer function)."""
+    N, K = 32, 16
+    n = 5
+    rng = np.random.default_rng(3)
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 0.0, seed=75, B=1)
+    W = rng.uniform(0.6, 1.2, (1, 2, n, N))
+    l2, g2 = O.wbp_grad(llr, fr, u, 1, W, kind=2, scale=1.0)
+    l0, g0 = O.wbp_grad(llr, fr, u, 1, W, kind=0, scale=1.0)
+    assert abs(l2 - (1.0 - np.exp(-l0))) <= 1e-14
+    np.testing.assert_allclose(g2, np.exp(-l0) * g0, rtol=1e-12, atol=1e-300)
+
+
+def test_wbp_frame_loss_gradient_matches_finite_differences():
+    """Weight and channel-LLR gradients of the frame-failure loss against
+    central differences on the double oracle (channel LLRs on a 2^-12 grid,
+    perturbed by +-2^-12, so every input stays an exact float32)."""
+    N, T, K = 16, 3, 8
+    n = 4
+    rng = np.random.default_rng(29)
+    fr = O.ga_frozen(N, K, 0.0, 0.5)
+    info = rng.integers(0, 2, (3, K)).astype(np.uint8)
+    u, x = O.encode_batch(info, K, 0, 0, fr)
+    llr = O.channel_llr(x, rng.standard_normal((3, N)), O.sigma2(-1.0, 0.5)).astype(np.float64)
+    h = 2.0 ** -12
+    llr = (np.round(llr / h) * h).astype(np.float32)
+    W = rng.uniform(0.5, 1.5, (T, 2, n, N))
+    loss, dW, dl = O.wbp_grad(llr, fr, u, T, W, kind=2, want_dllr=True)
+    assert 0.05 < loss < 0.95
+    eps = 1e-6
+    flat = W.reshape(-1)
+    bad = 0
+    for q in rng.choice(flat.size, size=60, replace=False):
+        wp = flat.copy(); wp[q] += eps
+        wm = flat.copy(); wm[q] -= eps
+        fd = (O.wbp_grad(llr, fr, u, T, wp, kind=2)[0] - O.wbp_grad(llr, fr, u, T, wm, kind=2)[0]) / (2 * eps)
+        if abs(fd - dW.reshape(-1)[q]) > 1e-7 + 1e-5 * abs(fd):
+            bad += 1
+    assert bad <= 1, bad
+    assert np.abs(dW).max() > 1e-4
+    bad = 0
+    for f in range(3):
+        for i in range(N):
+            lp = llr.copy(); lp[f, i] += np.float32(h)
+            lm = llr.copy(); lm[f, i] -= np.float32(h)
+            fd = (O.wbp_grad(lp, fr, u, T, W, kind=2)[0] - O.wbp_grad(lm, fr, u, T, W, kind=2)[0]) / (2 * h)
+            if abs(fd - dl[f, i]) > 1e-6 + 1e-4 * abs(fd):
+                bad += 1
+    assert bad <= 1, bad
+    assert np.count_nonzero(dl) >= 30
