@@ -365,6 +365,28 @@ polar_status wbp_bce(const polar_code* code, const float* llr_u, const uint8_t* 
 polar_status wbp_bce_multi(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B, int32_t T,
                            double scale, float* loss, float* dlam, hipStream_t stream);
 
+/* Frame-failure surrogate after every one of the T iterations: with S_t the
+ * binary cross-entropy above summed over the non-frozen positions of LLR(u)
+ * after iteration t (read from wbp_forward's saved rows, as wbp_bce_multi
+ * does), and the bits taken as independent, e^{-S_t} is the probability that
+ * all decisions after iteration t are right; the frame's loss is
+ * prod_t (1 - e^{-S_t}), the probability that no iteration gets the whole
+ * frame right -- a smooth stand-in for a BP failure within T iterations, the
+ * frames the hybrid of Sec. III hands to the list decoder.  loss dev [B] or
+ * NULL (times scale), dlam dev [B][T][N] = scale * d(loss)/d(LLR(u) after
+ * iteration t).  1 <= T <= 256.  Double precision inside, float stored.  Must
+ * run before wbp_backward, which overwrites `saved`. */
+polar_status wbp_frame_loss(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
+                            int32_t T, double scale, float* loss, float* dlam, hipStream_t stream);
+
+/* One weight per stage column (the column layout of bp_params): W dev
+ * [T][2][n][N] = Wc dev [T][2][n] repeated over the N nodes of each column
+ * (wbp_column_weights); dWc dev [T][2][n] = dW dev [T][2][n][N] summed over
+ * each column's nodes in node order, in double (wbp_column_grad) -- the
+ * gradient of a weight the whole column shares. */
+polar_status wbp_column_weights(const polar_code* code, const float* Wc, int32_t T, float* W, hipStream_t stream);
+polar_status wbp_column_grad(const polar_code* code, const float* dW, int32_t T, float* dWc, hipStream_t stream);
+
 /* Reverse-mode gradient of the weighted BP: dW dev [T][2][n][N] = sum over the
  * B frames (in frame order, accumulated in double) of d(loss)/dW given dlam
  * dev [B][dlam_iters][N]: d(loss)/d(llr_u) after the last iteration
@@ -380,6 +402,14 @@ polar_status wbp_backward(const polar_code* code, const float* llr, int64_t B, c
  * with bias corrections 1 - b^step.  All arrays dev, updated in place. */
 polar_status polar_adam_step(float* w, const float* g, float* m, float* v, int64_t count, int32_t step, float lr,
                              float beta1, float beta2, float eps, hipStream_t stream);
+
+/* The same step followed by a projection of each weight onto [lo, hi]
+ * (POLAR_ERR_INVALID_ARG unless lo <= hi).  The learned hybrid keeps its
+ * weights within [0, 1]: the decoder then never amplifies a check-node
+ * message and bp_decode_batch skips a clip that cannot act. */
+polar_status polar_adam_step_bounded(float* w, const float* g, float* m, float* v, int64_t count, int32_t step,
+                                     float lr, float beta1, float beta2, float eps, float lo, float hi,
+                                     hipStream_t stream);
 
 #ifdef __cplusplus
 }

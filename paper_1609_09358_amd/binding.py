@@ -69,6 +69,10 @@ def lib():
             "wbp_backward": [vp, vp, i64, vp, i32, C.c_float, i32, vp, vp, i32, vp, vp, vp],
             "wbp_bce_multi": [vp, vp, vp, i64, i32, C.c_double, vp, vp, vp],
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+            "polar_adam_step_bounded": [vp, vp, vp, vp, i64, i32] + [C.c_float] * 6 + [vp],
+            "wbp_frame_loss": [vp, vp, vp, i64, i32, C.c_double, vp, vp, vp],
+            "wbp_column_weights": [vp, vp, i32, vp, vp],
+            "wbp_column_grad": [vp, vp, i32, vp, vp],
             "polar_set_scl_lds_budget": [i64],
             "polar_set_pipeline_bp_occupancy": [i32],
             "polar_set_scl_ranking": [i32],
@@ -498,6 +502,44 @@ def wbp_bce_multi(code: PolarCode, saved, u_true, T, scale=None, want_loss=True)
     return loss, dlam
 
 
+def wbp_frame_loss(code: PolarCode, saved, u_true, T, scale=None, want_loss=True):
+    """Frame-failure surrogate prod_t (1 - exp(-S_t)) per frame (times scale)
+    and d loss / d LLR(u) after every iteration, [B][T][N]; scale defaults to
+    1/B.  Call before wbp_backward, which consumes `saved`."""
+    B = saved.shape[0]
+    _dev(saved, torch.float32, (B, T, 2, code.n, code.N), "saved")
+    _dev(u_true, torch.uint8, (B, code.N), "u_true")
+    if scale is None:
+        scale = 1.0 / B
+    dlam = torch.empty((B, T, code.N), dtype=torch.float32, device=saved.device)
+    loss = torch.empty(B, dtype=torch.float32, device=saved.device) if want_loss else None
+    _check(lib().wbp_frame_loss(code.handle, _ptr(saved), _ptr(u_true), B, T, float(scale), _ptr(loss), _ptr(dlam),
+                                _stream()))
+    return loss, dlam
+
+
+def wbp_column_weights(code: PolarCode, Wc, out=None):
+    """[T][2][n] column weights -> [T][2][n][N] per-node weights."""
+    T = Wc.shape[0]
+    _dev(Wc, torch.float32, (T, 2, code.n), "Wc")
+    if out is None:
+        out = torch.empty((T, 2, code.n, code.N), dtype=torch.float32, device=Wc.device)
+    _dev(out, torch.float32, (T, 2, code.n, code.N), "W")
+    _check(lib().wbp_column_weights(code.handle, _ptr(Wc), T, _ptr(out), _stream()))
+    return out
+
+
+def wbp_column_grad(code: PolarCode, dW, out=None):
+    """[T][2][n][N] per-node gradient -> [T][2][n] column sums."""
+    T = dW.shape[0]
+    _dev(dW, torch.float32, (T, 2, code.n, code.N), "dW")
+    if out is None:
+        out = torch.empty((T, 2, code.n), dtype=torch.float32, device=dW.device)
+    _dev(out, torch.float32, (T, 2, code.n), "dWc")
+    _check(lib().wbp_column_grad(code.handle, _ptr(dW), T, _ptr(out), _stream()))
+    return out
+
+
 def wbp_backward(code: PolarCode, llr, W, saved, dlam, llr_max=20.0, variant=0, want_dllr=False):
     """Weight gradient (summed over frames) and optionally d/d llr; `saved` is
     consumed.  dlam: [B][N] (loss after the last iteration) or [B][T][N]."""
@@ -520,6 +562,13 @@ def polar_adam_step(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
         _dev(t, torch.float32, tuple(w.shape), name)
     _check(lib().polar_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), int(step), lr, beta1, beta2, eps,
                                  _stream()))
+
+
+def polar_adam_step_bounded(w, g, m, v, step, lr=1e-3, lo=0.0, hi=1.0, beta1=0.9, beta2=0.999, eps=1e-8):
+    for name, t in (("w", w), ("g", g), ("m", m), ("v", v)):
+        _dev(t, torch.float32, tuple(w.shape), name)
+    _check(lib().polar_adam_step_bounded(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), int(step), lr, beta1, beta2,
+                                         eps, lo, hi, _stream()))
 
 
 class WeightedBPLoss(torch.autograd.Function):
@@ -550,7 +599,8 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "hybrid_decode_batch_static", "polar_set_hybrid_graphs",
             "polar_get_hybrid_graphs", "polar_workspace_size", "wbp_forward", "wbp_bce",
-            "wbp_backward", "wbp_bce_multi", "polar_adam_step", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
+            "wbp_backward", "wbp_bce_multi", "wbp_frame_loss", "wbp_column_weights", "wbp_column_grad",
+            "polar_adam_step", "polar_adam_step_bounded", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
             "polar_get_pipeline_bp_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",
             "polar_mixed_decode_graph", "polar_mixed_free"]

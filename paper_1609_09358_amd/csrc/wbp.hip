@@ -3,8 +3,10 @@
 //
 // Forward: bp_kernel with weights and message saving (bp.hip): T iterations,
 // no early stop, every produced row saved as saved[f][t][dir][s][node].
-// Loss: binary cross-entropy of P(u_i = 1) = sigmoid(-lambda_i) over the
-// non-frozen positions after the last iteration, lambda = L_{i,1} + R_{i,1}.
+// Losses: binary cross-entropy of P(u_i = 1) = sigmoid(-lambda_i) over the
+// non-frozen positions after the last iteration (or after every iteration),
+// lambda = L_{i,1} + R_{i,1}; or the frame-failure surrogate, the probability
+// (bits independent) that no iteration decides the whole frame right.
 // Adjoint (reverse mode, by hand): iterations T..1; inside one, the L sweep is
 // undone first (columns 0..n-1), then the R sweep (columns n-1..0), in the
 // same register windows as the forward: adjoint rows cross window boundaries
@@ -322,9 +324,91 @@ __global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const 
     }
 }
 
+constexpr int kFrameLossMaxT = 256;
+
+// Frame-failure surrogate of frame f (one workgroup).  S_t = sum over the
+// non-frozen i of softplus((2u_i - 1) lambda_{t,i}), lambda_{t,i} = saved L row
+// 0 of iteration t plus the frozen prior (0 where the loss reads); with the
+// bits taken as independent, e^{-S_t} is the probability that every decision
+// after iteration t is right, and loss = scale * prod_t (1 - e^{-S_t}) the
+// probability that none of the T iterations gets the frame right.
+// d loss / d lambda_{t,i} = scale * e^{-S_t} prod_{t' != t} (1 - e^{-S_t'})
+// * (2u_i - 1) sigmoid((2u_i - 1) lambda_{t,i}).  All in double.
+__global__ __launch_bounds__(256) void wbp_frame_loss_kernel(CodeDev code, const float* __restrict__ saved,
+                                                             const uint8_t* __restrict__ u, int T, double scale,
+                                                             float* __restrict__ loss, float* __restrict__ dlam) {
+    __shared__ double red[256 / 64];
+    __shared__ double S[kFrameLossMaxT];
+    const int64_t f = gid_x();
+    const int N = code.N, n = code.n;
+    const int nw = wg_size_x() / 64;
+    for (int t = 0; t < T; ++t) {
+        const float* lrow = saved + (((size_t)f * T + t) * 2 * n + n) * N;
+        double acc = 0.0;
+        for (int i = lid_x(); i < N; i += wg_size_x()) {
+            if ((code.frozen_bits[i >> 5] >> (i & 31)) & 1u) continue;
+            const float lam = lrow[i] + 0.0f;
+            const double z = (u[f * N + i] ? 1.0 : -1.0) * (double)lam;
+            acc += z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));
+        }
+        for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if ((lid_x() & 63) == 0) red[lid_x() >> 6] = acc;
+        __syncthreads();
+        if (lid_x() == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < nw; ++w) tot += red[w];
+            S[t] = tot;
+        }
+        __syncthreads();
+    }
+    if (loss && lid_x() == 0) {
+        double F = 1.0;
+        for (int t = 0; t < T; ++t) F *= -expm1(-S[t]);
+        loss[f] = (float)(F * scale);
+    }
+    for (int t = 0; t < T; ++t) {
+        double dS = exp(-S[t]);
+        for (int t2 = 0; t2 < T; ++t2)
+            if (t2 != t) dS *= -expm1(-S[t2]);
+        const float* lrow = saved + (((size_t)f * T + t) * 2 * n + n) * N;
+        float* drow = dlam + ((size_t)f * T + t) * N;
+        for (int i = lid_x(); i < N; i += wg_size_x()) {
+            float d = 0.0f;
+            if (!((code.frozen_bits[i >> 5] >> (i & 31)) & 1u)) {
+                const float lam = lrow[i] + 0.0f;
+                const double s = u[f * N + i] ? 1.0 : -1.0;
+                const double z = s * (double)lam;
+                const double sig = 1.0 / (1.0 + exp(-z));
+                d = (float)(scale * dS * s * sig);
+            }
+            drow[i] = d;
+        }
+    }
+}
+
+// W[t][d][s][i] = Wc[t][d][s]: one weight per stage column spread over its nodes
+__global__ __launch_bounds__(256) void wbp_expand_columns_kernel(const float* __restrict__ wc, int64_t cols, int N,
+                                                                 float* __restrict__ w) {
+    const int64_t q = gid_x() * wg_size_x() + lid_x();
+    if (q >= cols * N) return;
+    w[q] = wc[q / N];
+}
+
+// dWc[c] = sum over the N nodes of column c, in node order, in double: the
+// gradient of a weight shared by the whole column
+__global__ __launch_bounds__(256) void wbp_sum_columns_kernel(const float* __restrict__ dw, int64_t cols, int N,
+                                                              float* __restrict__ dwc) {
+    const int64_t c = gid_x() * wg_size_x() + lid_x();
+    if (c >= cols) return;
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += (double)dw[c * N + i];
+    dwc[c] = (float)acc;
+}
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t count,
-                                                   float lr, float b1, float b2, float eps, float c1, float c2) {
+                                                   float lr, float b1, float b2, float eps, float c1, float c2,
+                                                   float lo, float hi) {
     const int64_t q = gid_x() * wg_size_x() + lid_x();
     if (q >= count) return;
     const float gq = g[q];
@@ -333,7 +417,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const 
     m[q] = mq;
     v[q] = vq;
     const float mh = mq / c1, vh = vq / c2;
-    w[q] = w[q] - lr * mh / (sqrtf(vh) + eps);
+    w[q] = fminf(fmaxf(w[q] - lr * mh / (sqrtf(vh) + eps), lo), hi);
 }
 
 }  // namespace
@@ -400,14 +484,61 @@ extern "C" polar_status wbp_backward(const polar_code* code, const float* llr, i
     return st == POLAR_OK ? ok_status() : st;
 }
 
-extern "C" polar_status polar_adam_step(float* w, const float* g, float* m, float* v, int64_t count, int32_t step,
-                                        float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+static polar_status adam_launch(float* w, const float* g, float* m, float* v, int64_t count, int32_t step, float lr,
+                                float beta1, float beta2, float eps, float lo, float hi, hipStream_t stream) {
     if (!w || !g || !m || !v || count < 0 || step < 1) return set_error(POLAR_ERR_INVALID_ARG, "polar_adam_step: bad argument");
+    if (!(lo <= hi)) return set_error(POLAR_ERR_INVALID_ARG, "polar_adam_step_bounded: need lo <= hi");
     if (count == 0) return ok_status();
     const float c1 = (float)(1.0 - std::pow((double)beta1, step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, step));
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, w, g, m, v, count, lr,
-                       beta1, beta2, eps, c1, c2);
+                       beta1, beta2, eps, c1, c2, lo, hi);
     polar_status st = hip_check(hipGetLastError(), "adam launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
+extern "C" polar_status polar_adam_step(float* w, const float* g, float* m, float* v, int64_t count, int32_t step,
+                                        float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+    return adam_launch(w, g, m, v, count, step, lr, beta1, beta2, eps, -INFINITY, INFINITY, stream);
+}
+
+extern "C" polar_status polar_adam_step_bounded(float* w, const float* g, float* m, float* v, int64_t count,
+                                                int32_t step, float lr, float beta1, float beta2, float eps, float lo,
+                                                float hi, hipStream_t stream) {
+    return adam_launch(w, g, m, v, count, step, lr, beta1, beta2, eps, lo, hi, stream);
+}
+
+extern "C" polar_status wbp_frame_loss(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
+                                       int32_t T, double scale, float* loss, float* dlam, hipStream_t stream) {
+    if (!code || (B > 0 && (!saved || !u_true || !dlam)))
+        return set_error(POLAR_ERR_INVALID_ARG, "wbp_frame_loss: null argument");
+    if (B < 0 || T < 1 || T > kFrameLossMaxT || B > (int64_t)INT32_MAX)
+        return set_error(POLAR_ERR_INVALID_ARG, "wbp_frame_loss: bad sizes (1 <= T <= 256)");
+    if (B == 0) return ok_status();
+    hipLaunchKernelGGL(wbp_frame_loss_kernel, dim3((unsigned)B), dim3(256), 0, stream, code->dev(), saved, u_true, T,
+                       scale, loss, dlam);
+    polar_status st = hip_check(hipGetLastError(), "wbp_frame_loss launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
+extern "C" polar_status wbp_column_weights(const polar_code* code, const float* Wc, int32_t T, float* W,
+                                           hipStream_t stream) {
+    if (!code || !Wc || !W) return set_error(POLAR_ERR_INVALID_ARG, "wbp_column_weights: null argument");
+    if (T < 1) return set_error(POLAR_ERR_INVALID_ARG, "wbp_column_weights: T < 1");
+    const int64_t cols = (int64_t)T * 2 * code->n, tot = cols * code->N;
+    hipLaunchKernelGGL(wbp_expand_columns_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, Wc, cols,
+                       code->N, W);
+    polar_status st = hip_check(hipGetLastError(), "wbp_column_weights launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
+extern "C" polar_status wbp_column_grad(const polar_code* code, const float* dW, int32_t T, float* dWc,
+                                        hipStream_t stream) {
+    if (!code || !dW || !dWc) return set_error(POLAR_ERR_INVALID_ARG, "wbp_column_grad: null argument");
+    if (T < 1) return set_error(POLAR_ERR_INVALID_ARG, "wbp_column_grad: T < 1");
+    const int64_t cols = (int64_t)T * 2 * code->n;
+    hipLaunchKernelGGL(wbp_sum_columns_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, stream, dW, cols,
+                       code->N, dWc);
+    polar_status st = hip_check(hipGetLastError(), "wbp_column_grad launch");
     return st == POLAR_OK ? ok_status() : st;
 }

@@ -3,12 +3,16 @@
 Recipe (one step): draw a batch of random information bits and per-frame
 Eb/N0 uniform in [lo, hi] dB, encode (polar_encode), BPSK/AWGN LLRs
 (polar_channel_awgn), weighted BP forward with message saving (wbp_forward),
-binary cross-entropy on the non-frozen bits (wbp_bce), reverse-mode gradient
-(wbp_backward), Adam (polar_adam_step).  Every step of the decoder, its loss,
+binary cross-entropy on the non-frozen bits (wbp_bce, or after every
+iteration, wbp_bce_multi) or the frame-failure surrogate (wbp_frame_loss),
+reverse-mode gradient (wbp_backward), Adam (polar_adam_step, or projected onto
+a box, polar_adam_step_bounded).  Weights shared by a stage column are spread
+over its nodes (wbp_column_weights) and their gradient summed back
+(wbp_column_grad).  Every step of the decoder, its loss,
 gradient and update runs in the library's kernels; torch supplies device
 memory, the stream and the random draws of the workload.
 
-The weights start at 1 (plain min-sum BP) and are saved as float32 numpy
+The weights start at 1 (plain min-sum BP) unless told otherwise and are saved as float32 numpy
 arrays [T][2][n][N] together with the Adam moments and the step count, so a
 run can resume bit-exactly.
 """
@@ -29,13 +33,29 @@ def sigma2_of(ebn0_db: torch.Tensor, rate: float) -> torch.Tensor:
 
 
 class Trainer:
+    """Gradient training of the weighted BP with the library's kernels.
+
+    layout "node": one weight per edge output, W [T][2][n][N]; "column": one
+    weight per stage column, W [T][2][n] (the learned hybrid's form), spread
+    over the nodes by wbp_column_weights for the forward and adjoint, whose
+    per-node gradient wbp_column_grad sums back per column.
+    loss "bce": cross-entropy after the last iteration; "multi": summed over
+    iterations; "frame": the frame-failure surrogate (probability that no
+    iteration decides the whole frame right).
+    bounds (lo, hi): Adam projected onto that box (polar_adam_step_bounded).
+    w0: the initial weight (1 = plain min-sum BP)."""
+
     def __init__(self, code: PB.PolarCode, T: int, batch: int, lr: float = 1e-3, ebn0=(1.0, 4.0), seed: int = 1,
-                 llr_max: float = 20.0, multiloss: bool = False):
+                 llr_max: float = 20.0, multiloss: bool = False, layout: str = "node", loss: str = None,
+                 bounds=None, w0: float = 1.0):
         self.code, self.T, self.B, self.lr, self.ebn0, self.llr_max = code, T, batch, lr, ebn0, llr_max
-        self.multiloss = multiloss
+        self.loss = loss or ("multi" if multiloss else "bce")
+        assert self.loss in ("bce", "multi", "frame") and layout in ("node", "column")
+        self.layout, self.bounds = layout, bounds
         dev = torch.device("cuda")
-        shape = (T, 2, code.n, code.N)
-        self.W = torch.ones(shape, dtype=torch.float32, device=dev)
+        node_shape = (T, 2, code.n, code.N)
+        shape = node_shape if layout == "node" else (T, 2, code.n)
+        self.W = torch.full(shape, float(w0), dtype=torch.float32, device=dev)
         self.m = torch.zeros(shape, dtype=torch.float32, device=dev)
         self.v = torch.zeros(shape, dtype=torch.float32, device=dev)
         self.step = 0
@@ -43,10 +63,12 @@ class Trainer:
         self.gen.manual_seed(seed)
         self.out = dict(llr_u=torch.empty((batch, code.N), dtype=torch.float32, device=dev),
                         u_hat=torch.empty((batch, code.N), dtype=torch.uint8, device=dev),
-                        saved=torch.empty((batch,) + shape, dtype=torch.float32, device=dev))
+                        saved=torch.empty((batch,) + node_shape, dtype=torch.float32, device=dev))
+        self.Wn = torch.empty(node_shape, dtype=torch.float32, device=dev) if layout == "column" else None
+        self.dWc = torch.empty(shape, dtype=torch.float32, device=dev) if layout == "column" else None
 
     def frames(self, B=None, ebn0=None):
-        """A fresh batch: (u [B][N], llr [B][N])."""
+        """A fresh batch: (info [B][K], u [B][N], llr [B][N])."""
         B = B or self.B
         code = self.code
         info = torch.randint(0, 2, (B, code.K), generator=self.gen, device="cuda", dtype=torch.uint8)
@@ -57,16 +79,28 @@ class Trainer:
         llr = PB.polar_channel_awgn(x, z, sigma2_of(e, code.K / code.N).float().contiguous())
         return info, u, llr
 
+    def node_weights(self) -> torch.Tensor:
+        """The weights as the per-node kernels read them, [T][2][n][N]."""
+        return self.W if self.layout == "node" else PB.wbp_column_weights(self.code, self.W, out=self.Wn)
+
     def train_step(self):
         _, u, llr = self.frames()
-        fw = PB.wbp_forward(self.code, llr, self.W, llr_max=self.llr_max, save=True, out=self.out)
-        if self.multiloss:
+        Wn = self.node_weights()
+        fw = PB.wbp_forward(self.code, llr, Wn, llr_max=self.llr_max, save=True, out=self.out)
+        if self.loss == "multi":
             loss, dlam = PB.wbp_bce_multi(self.code, fw["saved"], u, self.T)
+        elif self.loss == "frame":
+            loss, dlam = PB.wbp_frame_loss(self.code, fw["saved"], u, self.T)
         else:
             loss, dlam = PB.wbp_bce(self.code, fw["llr_u"], u)
-        dW, _ = PB.wbp_backward(self.code, llr, self.W, fw["saved"], dlam, llr_max=self.llr_max)
+        dW, _ = PB.wbp_backward(self.code, llr, Wn, fw["saved"], dlam, llr_max=self.llr_max)
+        g = dW if self.layout == "node" else PB.wbp_column_grad(self.code, dW, out=self.dWc)
         self.step += 1
-        PB.polar_adam_step(self.W, dW, self.m, self.v, self.step, lr=self.lr)
+        if self.bounds is None:
+            PB.polar_adam_step(self.W, g, self.m, self.v, self.step, lr=self.lr)
+        else:
+            PB.polar_adam_step_bounded(self.W, g, self.m, self.v, self.step, lr=self.lr, lo=self.bounds[0],
+                                       hi=self.bounds[1])
         return loss
 
     def save(self, path):
@@ -99,6 +133,23 @@ def train(N=256, K=128, crc_bits=8, T=10, frames=1_000_000, batch=4096, lr=1e-3,
                 print(json.dumps({"step": s + 1, "loss": lv, "s": round(time.perf_counter() - t0, 2)}), flush=True)
     torch.cuda.synchronize()
     return tr, hist
+
+
+def train_front_end(code: PB.PolarCode, T: int, w0: float, ebn0: float, schedule=((3e-3, 1500), (1e-3, 1000)),
+                    batch: int = 1024, seed: int = 5):
+    """The learned hybrid's BP front end: one weight per stage column, from w0
+    everywhere (e.g. the normalized min-sum scale), trained by Adam on the
+    frame-failure loss at one Eb/N0, each weight kept within [0, 1];
+    schedule = ((lr, steps), ...).  Returns (trainer, frames seen)."""
+    tr = Trainer(code, T, batch, lr=schedule[0][0], ebn0=(ebn0, ebn0), seed=seed, layout="column", loss="frame",
+                 bounds=(0.0, 1.0), w0=w0)
+    seen = 0
+    for lr, steps in schedule:
+        tr.lr = lr
+        for _ in range(steps):
+            tr.train_step()
+        seen += steps * batch
+    return tr, seen
 
 
 def bp_fail_rate(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int, stop: int = 1, out=None) -> float:
