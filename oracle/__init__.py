@@ -54,7 +54,7 @@ def _lib(prec: str = "f64"):
         lib.orc_wbp_grad_frame.restype = C.c_double
         lib.orc_wbp_grad_batch.restype = C.c_double
         lib.orc_wbp_grad_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int,
-                                           C.c_double, _f64p, C.c_double, C.c_int, _f64p, _f64p]
+                                           C.c_double, _f64p, C.c_double, C.c_int, C.c_double, _f64p, _f64p]
         lib.orc_wbp_backward_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, C.c_int, C.c_double, _f64p,
                                                _f64p, C.c_int, _f64p, _f64p]
         lib.orc_adam_step.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double,
@@ -288,15 +288,18 @@ def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, pre
 
 
 def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", want_dllr=False, multi=False,
-             kind=None):
+             kind=None, fail_weight=0.0):
     """Loss and gradients of the weighted BP (batch).  Returns (loss, dW[, dllr]).
 
     kind 0 (default): the BCE of LLR(u) after the last iteration; kind 1
     (or multi=True): the sum of that BCE after every iteration; kind 2: the
     frame-failure surrogate prod_t (1 - exp(-S_t)), S_t the frame's BCE sum
-    after iteration t.  scale defaults to 1 / (B * k) for kind 0, 1 / (B * k * T)
-    for kind 1 (means over frames, non-frozen bits and iterations) and 1 / B
-    for kind 2 (the mean over frames)."""
+    after iteration t; kind 3: sum_{u<T} P_u + fail_weight * P_T with
+    P_u = prod_{t<=u} (1 - exp(-S_t)) (expected iterations beyond the first of
+    an early-stopping decoder, plus a price on frames still undecided after
+    T).  scale defaults to 1 / (B * k) for kind 0, 1 / (B * k * T) for kind 1
+    (means over frames, non-frozen bits and iterations) and 1 / B for kinds 2
+    and 3 (the mean over frames)."""
     kind = (1 if multi else 0) if kind is None else int(kind)
     fr = _u8(frozen)
     N = len(fr)
@@ -306,12 +309,12 @@ def wbp_grad(llr, frozen, u_true, T, W, llr_max=20.0, scale=None, prec="f64", wa
     B = llr.shape[0]
     k = int((fr == 0).sum())
     if scale is None:
-        scale = {0: 1.0 / (B * k), 1: 1.0 / (B * k * T), 2: 1.0 / B}[kind]
+        scale = {0: 1.0 / (B * k), 1: 1.0 / (B * k * T), 2: 1.0 / B, 3: 1.0 / B}[kind]
     W = _f64(W).reshape(T, 2, n, N)
     dW = np.zeros((T, 2, n, N), np.float64)
     dl = np.zeros((B, N), np.float64) if want_dllr else None
     loss = _lib(prec).orc_wbp_grad_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(u_true, _u8p),
-                                         T, llr_max, _p(W, _f64p), scale, kind, _p(dW, _f64p),
+                                         T, llr_max, _p(W, _f64p), scale, kind, float(fail_weight), _p(dW, _f64p),
                                          _p(dl, _f64p))
     if want_dllr:
         return loss, dW, dl

@@ -692,7 +692,13 @@ void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
 /*           every non-frozen decision after iteration t is right, so the     */
 /*           product is the probability that no iteration gets the whole     */
 /*           frame right -- a smooth stand-in for a BP failure within T       */
-/*           iterations (the frames the hybrid hands to the list decoder).    */
+/*           iterations (the frames the hybrid hands to the list decoder);    */
+/*   kind 3: sum_{u=1}^{T-1} P_u + c P_T, P_u = prod_{t<=u} (1 - exp(-S_t)), */
+/*           c = fail_weight: P_u is the probability (same independence)     */
+/*           that the frame is still undecided after iteration u, so the sum  */
+/*           is the expected number of iterations beyond the first that an   */
+/*           early-stopping decoder runs, and c P_T (c times the kind-2 loss) */
+/*           prices a frame handed to the list decoder at c iterations.       */
 /* Backward (reverse mode, by hand): iterations T..1; inside one, the L sweep */
 /* is undone first (s = 0..n-1), then the R sweep (s = n-1..0).  Rules:       */
 /*   d clip(p)/dp = 1 if |p| <= LLR_max (inclusive), else 0;                  */
@@ -833,7 +839,7 @@ void orc_wbp_backward_frame(const float* llr, int N, const uint8_t* frozen, int 
 }
 
 double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t* u_true,
-                          int T, double llr_max, const double* W, double scale, int kind,
+                          int T, double llr_max, const double* W, double scale, int kind, double fail_weight,
                           double* dW /* [T][2][n][N], accumulated */, double* dllr /* N or NULL */) {
     int n = ilog2(N);
     size_t per = (size_t)2 * n * N;
@@ -874,13 +880,45 @@ double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const 
                 double sgn_u = u_true[i] ? 1.0 : -1.0;
                 S[t] += softplus(sgn_u * lt[(size_t)t * N + i]);
             }
+        /* q_t = 1 - e^{-S_t}: the probability that iteration t leaves some decision wrong */
+        double* q = (double*)malloc(sizeof(double) * T);
+        for (int t = 0; t < T; t++) q[t] = -expm1(-S[t]);
         double F = 1.0;
-        for (int t = 0; t < T; t++) F *= -expm1(-S[t]);
-        loss = F;
+        for (int t = 0; t < T; t++) F *= q[t];
+        if (kind == 2) {
+            loss = F;
+        } else {
+            /* sum over u = 1..T-1 (iterations counted from 1) of P_u, plus c P_T */
+            loss = 0.0;
+            for (int u = 0; u < T - 1; u++) {
+                double P = 1.0;
+                for (int t = 0; t <= u; t++) P *= q[t];
+                loss += P;
+            }
+            loss += fail_weight * F;
+        }
         for (int t = 0; t < T; t++) {
-            double dS = exp(-S[t]);
-            for (int t2 = 0; t2 < T; t2++)
-                if (t2 != t) dS *= -expm1(-S[t2]);
+            /* d loss / d S_t: dq_t/dS_t = e^{-S_t}, times every product that holds q_t
+               with q_t taken out */
+            double dS;
+            if (kind == 2) {
+                dS = exp(-S[t]);
+                for (int t2 = 0; t2 < T; t2++)
+                    if (t2 != t) dS *= q[t2];
+            } else {
+                double acc = 0.0;
+                for (int u = t; u < T - 1; u++) {
+                    double P = 1.0;
+                    for (int t2 = 0; t2 <= u; t2++)
+                        if (t2 != t) P *= q[t2];
+                    acc += P;
+                }
+                double PT = 1.0;
+                for (int t2 = 0; t2 < T; t2++)
+                    if (t2 != t) PT *= q[t2];
+                acc += fail_weight * PT;
+                dS = exp(-S[t]) * acc;
+            }
             for (int i = 0; i < N; i++) {
                 if (frozen[i]) continue;
                 double sgn_u = u_true[i] ? 1.0 : -1.0;
@@ -889,6 +927,7 @@ double orc_wbp_grad_frame(const float* llr, int N, const uint8_t* frozen, const 
                 dlam[(size_t)t * N + i] = (double)(real)(scale * dS * sgn_u * sig);
             }
         }
+        free(q);
         free(S);
     }
     orc_wbp_backward_frame(llr, N, frozen, T, llr_max, W, dlam, nl, dW, dllr);
@@ -909,11 +948,11 @@ void orc_wbp_backward_batch(const float* llr, int64_t B, int N, const uint8_t* f
 
 double orc_wbp_grad_batch(const float* llr, int64_t B, int N, const uint8_t* frozen,
                           const uint8_t* u_true, int T, double llr_max, const double* W,
-                          double scale, int kind, double* dW, double* dllr) {
+                          double scale, int kind, double fail_weight, double* dW, double* dllr) {
     double loss = 0.0;
     for (int64_t f = 0; f < B; f++)
-        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, kind, dW,
-                                   dllr ? dllr + f * N : NULL);
+        loss += orc_wbp_grad_frame(llr + f * N, N, frozen, u_true + f * N, T, llr_max, W, scale, kind,
+                                   fail_weight, dW, dllr ? dllr + f * N : NULL);
     return loss;
 }
 

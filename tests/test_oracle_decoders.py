@@ -631,3 +631,88 @@ def test_wbp_frame_loss_gradient_matches_finite_differences():
                 bad += 1
     assert bad <= 1, bad
     assert np.count_nonzero(dl) >= 30
+
+
+def test_wbp_iteration_loss_value():
+    """Loss kind 3: sum over u < T of P_u plus c P_T, P_u = prod_{t<=u}
+    (1 - exp(-S_t)) with S_t from separate truncated decodes; noiseless frames
+    cost nothing, hopeless ones T - 1 + c."""
+    N, K, T, c = 64, 32, 5, 7.5
+    n = 6
+    rng = np.random.default_rng(23)
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 0.5, seed=76, B=6)
+    W = rng.uniform(0.6, 1.2, (T, 2, n, N))
+    loss = O.wbp_grad(llr, fr, u, T, W, kind=3, fail_weight=c)[0]
+    S = _truncated_S(llr, fr, u, W, T)
+    P = np.cumprod(1.0 - np.exp(-S), axis=1)
+    ref = np.mean(P[:, :-1].sum(axis=1) + c * P[:, -1])
+    assert abs(loss - ref) <= 1e-12 * max(1.0, ref)
+    # noiseless frames at the clip level, plain min-sum: every iteration is
+    # right with certainty, so nothing is left to pay
+    ones = np.ones_like(W)
+    clean = np.where(x == 0, 20.0, -20.0).astype(np.float32)
+    assert O.wbp_grad(clean, fr, u, T, ones, kind=3, fail_weight=c)[0] < 1e-6
+    wrong = np.where(x == 0, -20.0, 20.0).astype(np.float32)  # every channel value points the wrong way
+    lw = O.wbp_grad(wrong, fr, u, T, ones, kind=3, fail_weight=c)[0]
+    assert abs(lw - (T - 1 + c)) < 1e-6
+
+
+def test_wbp_iteration_loss_affine_in_fail_weight():
+    """The fail-weight term is the kind-2 loss: L(c1) - L(c2) = (c1 - c2) F for
+    the value and the gradient; at T = 1 the loss is c F exactly."""
+    N, K, T = 32, 16, 4
+    n = 5
+    rng = np.random.default_rng(6)
+    fr, info, u, x, llr = _frame(N, K, 0, 0, 0.0, seed=77, B=3)
+    W = rng.uniform(0.6, 1.2, (T, 2, n, N))
+    l1, g1 = O.wbp_grad(llr, fr, u, T, W, kind=3, fail_weight=9.0)
+    l2, g2 = O.wbp_grad(llr, fr, u, T, W, kind=3, fail_weight=2.0)
+    lf, gf = O.wbp_grad(llr, fr, u, T, W, kind=2)
+    assert abs((l1 - l2) - 7.0 * lf) <= 1e-12 * max(1.0, abs(l1))
+    np.testing.assert_allclose(g1 - g2, 7.0 * gf, rtol=1e-9, atol=1e-14 * np.abs(g1).max())
+    W1 = W[:1]
+    l3, g3 = O.wbp_grad(llr, fr, u, 1, W1, kind=3, fail_weight=3.0)
+    l4, g4 = O.wbp_grad(llr, fr, u, 1, W1, kind=2)
+    assert abs(l3 - 3.0 * l4) <= 1e-14
+    np.testing.assert_allclose(g3, 3.0 * g4, rtol=1e-12, atol=1e-300)
+
+
+def test_wbp_iteration_loss_gradient_matches_finite_differences():
+    """Weight and channel-LLR gradients of the iteration loss against central
+    differences on the double oracle (LLRs on a 2^-12 grid perturbed by
+    +-2^-12, exact float32 inputs)."""
+    N, T, K, c = 16, 3, 8, 5.0
+    n = 4
+    rng = np.random.default_rng(31)
+    fr = O.ga_frozen(N, K, 0.0, 0.5)
+    info = rng.integers(0, 2, (3, K)).astype(np.uint8)
+    u, x = O.encode_batch(info, K, 0, 0, fr)
+    llr = O.channel_llr(x, rng.standard_normal((3, N)), O.sigma2(-1.0, 0.5)).astype(np.float64)
+    h = 2.0 ** -12
+    llr = (np.round(llr / h) * h).astype(np.float32)
+    W = rng.uniform(0.5, 1.5, (T, 2, n, N))
+    loss, dW, dl = O.wbp_grad(llr, fr, u, T, W, kind=3, fail_weight=c, want_dllr=True)
+    assert 0.05 < loss < T - 1 + c - 0.05
+    eps = 1e-6
+    flat = W.reshape(-1)
+    bad = 0
+    for q in rng.choice(flat.size, size=60, replace=False):
+        wp = flat.copy(); wp[q] += eps
+        wm = flat.copy(); wm[q] -= eps
+        fd = (O.wbp_grad(llr, fr, u, T, wp, kind=3, fail_weight=c)[0]
+              - O.wbp_grad(llr, fr, u, T, wm, kind=3, fail_weight=c)[0]) / (2 * eps)
+        if abs(fd - dW.reshape(-1)[q]) > 1e-7 + 1e-5 * abs(fd):
+            bad += 1
+    assert bad <= 1, bad
+    assert np.abs(dW).max() > 1e-4
+    bad = 0
+    for f in range(3):
+        for i in range(N):
+            lp = llr.copy(); lp[f, i] += np.float32(h)
+            lm = llr.copy(); lm[f, i] -= np.float32(h)
+            fd = (O.wbp_grad(lp, fr, u, T, W, kind=3, fail_weight=c)[0]
+                  - O.wbp_grad(lm, fr, u, T, W, kind=3, fail_weight=c)[0]) / (2 * h)
+            if abs(fd - dl[f, i]) > 1e-6 + 1e-4 * abs(fd):
+                bad += 1
+    assert bad <= 1, bad
+    assert np.count_nonzero(dl) >= 30
