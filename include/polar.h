@@ -379,6 +379,19 @@ polar_status wbp_bce_multi(const polar_code* code, const float* saved, const uin
 polar_status wbp_frame_loss(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
                             int32_t T, double scale, float* loss, float* dlam, hipStream_t stream);
 
+/* Expected-iterations loss of an early-stopping decoder: with q_t = 1 -
+ * e^{-S_t} as above and P_u = prod_{t<=u} q_t the probability (bits taken as
+ * independent) that the frame is still undecided after iteration u, the
+ * frame's loss is sum_{u<T} P_u + fail_weight * P_T: the expected number of
+ * iterations beyond the first that a decoder stopping at the first right
+ * iteration runs, plus fail_weight per frame still undecided after T (the
+ * hybrid of Sec. III then runs the list decoder, which costs about as much as
+ * fail_weight iterations).  Same arguments as wbp_frame_loss; fail_weight >= 0
+ * (POLAR_ERR_INVALID_ARG otherwise). */
+polar_status wbp_iteration_loss(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
+                                int32_t T, double fail_weight, double scale, float* loss, float* dlam,
+                                hipStream_t stream);
+
 /* One weight per stage column (the column layout of bp_params): W dev
  * [T][2][n][N] = Wc dev [T][2][n] repeated over the N nodes of each column
  * (wbp_column_weights); dWc dev [T][2][n] = dW dev [T][2][n][N] summed over

@@ -71,6 +71,7 @@ def lib():
             "polar_adam_step": [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "polar_adam_step_bounded": [vp, vp, vp, vp, i64, i32] + [C.c_float] * 6 + [vp],
             "wbp_frame_loss": [vp, vp, vp, i64, i32, C.c_double, vp, vp, vp],
+            "wbp_iteration_loss": [vp, vp, vp, i64, i32, C.c_double, C.c_double, vp, vp, vp],
             "wbp_column_weights": [vp, vp, i32, vp, vp],
             "wbp_column_grad": [vp, vp, i32, vp, vp],
             "polar_set_scl_lds_budget": [i64],
@@ -518,6 +519,22 @@ def wbp_frame_loss(code: PolarCode, saved, u_true, T, scale=None, want_loss=True
     return loss, dlam
 
 
+def wbp_iteration_loss(code: PolarCode, saved, u_true, T, fail_weight, scale=None, want_loss=True):
+    """Expected-iterations loss sum_{u<T} P_u + fail_weight * P_T per frame
+    (times scale) and d loss / d LLR(u) after every iteration, [B][T][N];
+    scale defaults to 1/B.  Call before wbp_backward, which consumes `saved`."""
+    B = saved.shape[0]
+    _dev(saved, torch.float32, (B, T, 2, code.n, code.N), "saved")
+    _dev(u_true, torch.uint8, (B, code.N), "u_true")
+    if scale is None:
+        scale = 1.0 / B
+    dlam = torch.empty((B, T, code.N), dtype=torch.float32, device=saved.device)
+    loss = torch.empty(B, dtype=torch.float32, device=saved.device) if want_loss else None
+    _check(lib().wbp_iteration_loss(code.handle, _ptr(saved), _ptr(u_true), B, T, float(fail_weight), float(scale),
+                                    _ptr(loss), _ptr(dlam), _stream()))
+    return loss, dlam
+
+
 def wbp_column_weights(code: PolarCode, Wc, out=None):
     """[T][2][n] column weights -> [T][2][n][N] per-node weights."""
     T = Wc.shape[0]
@@ -599,7 +616,7 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "polar_encode", "polar_channel_awgn", "bp_decode_batch", "polar_bp_variants", "scl_decode_batch",
             "hybrid_decode_batch", "hybrid_decode_batch_static", "polar_set_hybrid_graphs",
             "polar_get_hybrid_graphs", "polar_workspace_size", "wbp_forward", "wbp_bce",
-            "wbp_backward", "wbp_bce_multi", "wbp_frame_loss", "wbp_column_weights", "wbp_column_grad",
+            "wbp_backward", "wbp_bce_multi", "wbp_frame_loss", "wbp_iteration_loss", "wbp_column_weights", "wbp_column_grad",
             "polar_adam_step", "polar_adam_step_bounded", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
             "polar_get_pipeline_bp_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",

@@ -326,19 +326,28 @@ __global__ __launch_bounds__(256) void wbp_bce_multi_kernel(CodeDev code, const 
 
 constexpr int kFrameLossMaxT = 256;
 
-// Frame-failure surrogate of frame f (one workgroup).  S_t = sum over the
+// Frame-level losses of frame f (one workgroup), from S_t = sum over the
 // non-frozen i of softplus((2u_i - 1) lambda_{t,i}), lambda_{t,i} = saved L row
-// 0 of iteration t plus the frozen prior (0 where the loss reads); with the
-// bits taken as independent, e^{-S_t} is the probability that every decision
-// after iteration t is right, and loss = scale * prod_t (1 - e^{-S_t}) the
-// probability that none of the T iterations gets the frame right.
-// d loss / d lambda_{t,i} = scale * e^{-S_t} prod_{t' != t} (1 - e^{-S_t'})
-// * (2u_i - 1) sigmoid((2u_i - 1) lambda_{t,i}).  All in double.
+// 0 of iteration t plus the frozen prior (0 where the loss reads).  With the
+// bits taken as independent, q_t = 1 - e^{-S_t} is the probability that some
+// decision after iteration t is wrong, and P_u = prod_{t<=u} q_t that the frame
+// is still undecided after iteration u.
+//   ITER = false: loss = P_T, the probability that no iteration gets the
+//     frame right (a smooth stand-in for a BP failure within T iterations);
+//   ITER = true:  loss = sum_{u<T} P_u + c P_T, the expected number of
+//     iterations beyond the first of an early-stopping decoder plus c per
+//     frame still undecided after T (c = fail_weight).
+// d loss / d lambda_{t,i} = scale * d loss / d S_t * (2u_i - 1)
+// sigmoid((2u_i - 1) lambda_{t,i}), where d loss / d S_t = e^{-S_t} times the
+// sum of the products that hold q_t, with q_t taken out.  All in double.
+template <bool ITER>
 __global__ __launch_bounds__(256) void wbp_frame_loss_kernel(CodeDev code, const float* __restrict__ saved,
                                                              const uint8_t* __restrict__ u, int T, double scale,
-                                                             float* __restrict__ loss, float* __restrict__ dlam) {
+                                                             double fail_weight, float* __restrict__ loss,
+                                                             float* __restrict__ dlam) {
     __shared__ double red[256 / 64];
     __shared__ double S[kFrameLossMaxT];
+    __shared__ double q[kFrameLossMaxT];
     const int64_t f = gid_x();
     const int N = code.N, n = code.n;
     const int nw = wg_size_x() / 64;
@@ -358,28 +367,55 @@ __global__ __launch_bounds__(256) void wbp_frame_loss_kernel(CodeDev code, const
             double tot = 0.0;
             for (int w = 0; w < nw; ++w) tot += red[w];
             S[t] = tot;
+            q[t] = -expm1(-tot);
         }
         __syncthreads();
     }
     if (loss && lid_x() == 0) {
         double F = 1.0;
-        for (int t = 0; t < T; ++t) F *= -expm1(-S[t]);
-        loss[f] = (float)(F * scale);
+        for (int t = 0; t < T; ++t) F *= q[t];
+        double L = F;
+        if (ITER) {
+            L = 0.0;
+            for (int v = 0; v < T - 1; ++v) {
+                double P = 1.0;
+                for (int t = 0; t <= v; ++t) P *= q[t];
+                L += P;
+            }
+            L += fail_weight * F;
+        }
+        loss[f] = (float)(L * scale);
     }
     for (int t = 0; t < T; ++t) {
-        double dS = exp(-S[t]);
-        for (int t2 = 0; t2 < T; ++t2)
-            if (t2 != t) dS *= -expm1(-S[t2]);
+        double dS;
+        if (!ITER) {
+            dS = exp(-S[t]);
+            for (int t2 = 0; t2 < T; ++t2)
+                if (t2 != t) dS *= q[t2];
+        } else {
+            double acc = 0.0;
+            for (int v = t; v < T - 1; ++v) {
+                double P = 1.0;
+                for (int t2 = 0; t2 <= v; ++t2)
+                    if (t2 != t) P *= q[t2];
+                acc += P;
+            }
+            double PT = 1.0;
+            for (int t2 = 0; t2 < T; ++t2)
+                if (t2 != t) PT *= q[t2];
+            acc += fail_weight * PT;
+            dS = exp(-S[t]) * acc;
+        }
         const float* lrow = saved + (((size_t)f * T + t) * 2 * n + n) * N;
         float* drow = dlam + ((size_t)f * T + t) * N;
         for (int i = lid_x(); i < N; i += wg_size_x()) {
             float d = 0.0f;
             if (!((code.frozen_bits[i >> 5] >> (i & 31)) & 1u)) {
                 const float lam = lrow[i] + 0.0f;
-                const double s = u[f * N + i] ? 1.0 : -1.0;
-                const double z = s * (double)lam;
+                const double sg = u[f * N + i] ? 1.0 : -1.0;
+                const double z = sg * (double)lam;
                 const double sig = 1.0 / (1.0 + exp(-z));
-                d = (float)(scale * dS * s * sig);
+                d = (float)(scale * dS * sg * sig);
             }
             drow[i] = d;
         }
@@ -508,17 +544,35 @@ extern "C" polar_status polar_adam_step_bounded(float* w, const float* g, float*
     return adam_launch(w, g, m, v, count, step, lr, beta1, beta2, eps, lo, hi, stream);
 }
 
+static polar_status frame_loss_launch(const char* who, bool iter, const polar_code* code, const float* saved,
+                                      const uint8_t* u_true, int64_t B, int32_t T, double fail_weight, double scale,
+                                      float* loss, float* dlam, hipStream_t stream) {
+    if (!code || (B > 0 && (!saved || !u_true || !dlam)))
+        return set_error(POLAR_ERR_INVALID_ARG, std::string(who) + ": null argument");
+    if (B < 0 || T < 1 || T > kFrameLossMaxT || B > (int64_t)INT32_MAX)
+        return set_error(POLAR_ERR_INVALID_ARG, std::string(who) + ": bad sizes (1 <= T <= 256)");
+    if (!(fail_weight >= 0.0)) return set_error(POLAR_ERR_INVALID_ARG, std::string(who) + ": fail_weight < 0");
+    if (B == 0) return ok_status();
+    if (iter)
+        hipLaunchKernelGGL(wbp_frame_loss_kernel<true>, dim3((unsigned)B), dim3(256), 0, stream, code->dev(), saved,
+                           u_true, T, scale, fail_weight, loss, dlam);
+    else
+        hipLaunchKernelGGL(wbp_frame_loss_kernel<false>, dim3((unsigned)B), dim3(256), 0, stream, code->dev(), saved,
+                           u_true, T, scale, fail_weight, loss, dlam);
+    polar_status st = hip_check(hipGetLastError(), "frame loss launch");
+    return st == POLAR_OK ? ok_status() : st;
+}
+
 extern "C" polar_status wbp_frame_loss(const polar_code* code, const float* saved, const uint8_t* u_true, int64_t B,
                                        int32_t T, double scale, float* loss, float* dlam, hipStream_t stream) {
-    if (!code || (B > 0 && (!saved || !u_true || !dlam)))
-        return set_error(POLAR_ERR_INVALID_ARG, "wbp_frame_loss: null argument");
-    if (B < 0 || T < 1 || T > kFrameLossMaxT || B > (int64_t)INT32_MAX)
-        return set_error(POLAR_ERR_INVALID_ARG, "wbp_frame_loss: bad sizes (1 <= T <= 256)");
-    if (B == 0) return ok_status();
-    hipLaunchKernelGGL(wbp_frame_loss_kernel, dim3((unsigned)B), dim3(256), 0, stream, code->dev(), saved, u_true, T,
-                       scale, loss, dlam);
-    polar_status st = hip_check(hipGetLastError(), "wbp_frame_loss launch");
-    return st == POLAR_OK ? ok_status() : st;
+    return frame_loss_launch("wbp_frame_loss", false, code, saved, u_true, B, T, 0.0, scale, loss, dlam, stream);
+}
+
+extern "C" polar_status wbp_iteration_loss(const polar_code* code, const float* saved, const uint8_t* u_true,
+                                           int64_t B, int32_t T, double fail_weight, double scale, float* loss,
+                                           float* dlam, hipStream_t stream) {
+    return frame_loss_launch("wbp_iteration_loss", true, code, saved, u_true, B, T, fail_weight, scale, loss, dlam,
+                             stream);
 }
 
 extern "C" polar_status wbp_column_weights(const polar_code* code, const float* Wc, int32_t T, float* W,

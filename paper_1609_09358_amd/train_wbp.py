@@ -41,17 +41,19 @@ class Trainer:
     per-node gradient wbp_column_grad sums back per column.
     loss "bce": cross-entropy after the last iteration; "multi": summed over
     iterations; "frame": the frame-failure surrogate (probability that no
-    iteration decides the whole frame right).
+    iteration decides the whole frame right); "iter": the expected iterations
+    of an early-stopping decoder plus fail_weight per frame left undecided
+    after T.
     bounds (lo, hi): Adam projected onto that box (polar_adam_step_bounded).
     w0: the initial weight (1 = plain min-sum BP)."""
 
     def __init__(self, code: PB.PolarCode, T: int, batch: int, lr: float = 1e-3, ebn0=(1.0, 4.0), seed: int = 1,
                  llr_max: float = 20.0, multiloss: bool = False, layout: str = "node", loss: str = None,
-                 bounds=None, w0: float = 1.0):
+                 bounds=None, w0: float = 1.0, fail_weight: float = 0.0):
         self.code, self.T, self.B, self.lr, self.ebn0, self.llr_max = code, T, batch, lr, ebn0, llr_max
         self.loss = loss or ("multi" if multiloss else "bce")
-        assert self.loss in ("bce", "multi", "frame") and layout in ("node", "column")
-        self.layout, self.bounds = layout, bounds
+        assert self.loss in ("bce", "multi", "frame", "iter") and layout in ("node", "column")
+        self.layout, self.bounds, self.fail_weight = layout, bounds, fail_weight
         dev = torch.device("cuda")
         node_shape = (T, 2, code.n, code.N)
         shape = node_shape if layout == "node" else (T, 2, code.n)
@@ -91,6 +93,8 @@ class Trainer:
             loss, dlam = PB.wbp_bce_multi(self.code, fw["saved"], u, self.T)
         elif self.loss == "frame":
             loss, dlam = PB.wbp_frame_loss(self.code, fw["saved"], u, self.T)
+        elif self.loss == "iter":
+            loss, dlam = PB.wbp_iteration_loss(self.code, fw["saved"], u, self.T, self.fail_weight)
         else:
             loss, dlam = PB.wbp_bce(self.code, fw["llr_u"], u)
         dW, _ = PB.wbp_backward(self.code, llr, Wn, fw["saved"], dlam, llr_max=self.llr_max)
@@ -135,14 +139,18 @@ def train(N=256, K=128, crc_bits=8, T=10, frames=1_000_000, batch=4096, lr=1e-3,
     return tr, hist
 
 
-def train_front_end(code: PB.PolarCode, T: int, w0: float, ebn0: float, schedule=((3e-3, 1500), (1e-3, 1000)),
-                    batch: int = 1024, seed: int = 5):
+def train_front_end(code: PB.PolarCode, T: int, w0, ebn0: float, schedule=((3e-3, 1500), (1e-3, 1000)),
+                    batch: int = 1024, seed: int = 5, loss: str = "frame", fail_weight: float = 0.0):
     """The learned hybrid's BP front end: one weight per stage column, from w0
-    everywhere (e.g. the normalized min-sum scale), trained by Adam on the
-    frame-failure loss at one Eb/N0, each weight kept within [0, 1];
-    schedule = ((lr, steps), ...).  Returns (trainer, frames seen)."""
-    tr = Trainer(code, T, batch, lr=schedule[0][0], ebn0=(ebn0, ebn0), seed=seed, layout="column", loss="frame",
-                 bounds=(0.0, 1.0), w0=w0)
+    (a number for every weight, e.g. the normalized min-sum scale, or a
+    [T][2][n] tensor), trained by Adam on the frame-failure loss (or the
+    expected-iterations loss with fail_weight) at one Eb/N0, each weight kept
+    within [0, 1]; schedule = ((lr, steps), ...).  Returns (trainer, frames
+    seen)."""
+    tr = Trainer(code, T, batch, lr=schedule[0][0], ebn0=(ebn0, ebn0), seed=seed, layout="column", loss=loss,
+                 bounds=(0.0, 1.0), w0=1.0 if torch.is_tensor(w0) else w0, fail_weight=fail_weight)
+    if torch.is_tensor(w0):
+        tr.W.copy_(w0)
     seen = 0
     for lr, steps in schedule:
         tr.lr = lr

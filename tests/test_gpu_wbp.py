@@ -256,30 +256,36 @@ def test_frame_loss_backward_bit_exact_given_dlam(N, K, c, T):
 
 
 @pytest.mark.parametrize("T,ebn0", [(3, 0.5), (10, 1.5), (20, 2.5)])
-def test_frame_loss_end_to_end_vs_oracle(T, ebn0):
-    """Frame-failure loss and its weight gradient at N = 256 against the
-    oracle (kind 2 of its weighted-BP gradient): the loss per frame and the
+@pytest.mark.parametrize("kind,fw_c", [(2, 0.0), (3, 0.0), (3, 40.0)])
+def test_frame_loss_end_to_end_vs_oracle(T, ebn0, kind, fw_c):
+    """Frame-level losses and their weight gradients at N = 256 against the
+    oracle: the frame-failure loss (kind 2) and the expected-iterations loss
+    with and without a fail weight (kind 3).  The loss per frame and the
     gradient agree to float rounding with the float build at any T and with
     the double build at T = 3.  The Eb/N0 is chosen so that a good part of the
-    frames sit between 'always right' and 'never right', where the surrogate
-    has a gradient."""
+    frames sit between 'always right' and 'never right', where these losses
+    have a gradient."""
     N, K, c, B = 256, 128, 8, 64
     code, u, llr = frames(N, K, c, ebn0, B, seed=77 + T)
     W = rand_w(T, 8, N, seed=11, lo=0.8, hi=1.1)
     llr_d, W_d = dev(llr), dev(W)
     fw = PB.wbp_forward(code, llr_d, W_d, save=True)
-    loss, dlam = PB.wbp_frame_loss(code, fw["saved"], dev(u), T)
+    if kind == 2:
+        loss, dlam = PB.wbp_frame_loss(code, fw["saved"], dev(u), T)
+    else:
+        loss, dlam = PB.wbp_iteration_loss(code, fw["saved"], dev(u), T, fw_c)
     dW, _ = PB.wbp_backward(code, llr_d, W_d, fw["saved"], dlam)
     g = host(dW).astype(np.float64)
     per = host(loss).astype(np.float64)
-    assert np.all((per >= 0) & (per <= 1.0 / B))
+    top = 1.0 if kind == 2 else T - 1 + fw_c
+    assert np.all((per >= 0) & (per <= top / B * (1 + 1e-6)))
     tot = float(per.sum())
-    l32, g32 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), kind=2, prec="f32")
+    l32, g32 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), kind=kind, fail_weight=fw_c, prec="f32")
     assert abs(tot - l32) <= 1e-5 * max(1e-3, abs(l32))
     assert np.abs(g32).max() > 0
     assert np.max(np.abs(g - g32)) <= 1e-5 * np.abs(g32).max()
     if T <= 3:
-        l64, g64 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), kind=2)
+        l64, g64 = O.wbp_grad(llr, code.frozen, u, T, W.astype(np.float64), kind=kind, fail_weight=fw_c)
         assert abs(tot - l64) <= 1e-5 * max(1e-3, abs(l64))
         assert np.max(np.abs(g - g64)) <= 1e-4 * np.abs(g64).max()
 
