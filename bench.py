@@ -447,9 +447,10 @@ def kernel_times(code, llr, W, T, L, reps):
 
 
 def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
-    """List decoding with the pruned pseudo sort against a bitonic sort of the
-    candidates (Sec. II-A describes both), on the frames the learned BP failed
-    in one batch (latency-bound) and on 8192 frames (throughput-bound)."""
+    """List decoding with the pruned pseudo sort, a bitonic sort of the
+    candidates (Sec. II-A describes both) and threshold selection, on the
+    frames the learned BP failed in one batch (latency-bound) and on 8192
+    frames (throughput-bound)."""
     import torch
 
     from paper_1609_09358_amd import binding as PB
@@ -460,7 +461,7 @@ def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
     for L in (8, 32):
         for name, ids in (("failed_frames", fail), ("8192_frames", many)):
             row = {}
-            for mode in (1, 2):
+            for mode in (1, 2, 3):
                 PB.polar_set_scl_ranking(mode)
                 out = PB.scl_decode_batch(code, llr, L, frame_ids=ids)
                 torch.cuda.synchronize()
@@ -468,7 +469,8 @@ def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
                 for _ in range(reps):
                     PB.scl_decode_batch(code, llr, L, frame_ids=ids, out=out)
                 torch.cuda.synchronize()
-                row["bitonic_ms" if mode == 2 else "pseudo_sort_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+                row[{1: "pseudo_sort_ms", 2: "bitonic_ms", 3: "threshold_ms"}[mode]] = \
+                    round((time.perf_counter() - t0) / reps * 1e3, 3)
             res[f"L{L}_{name}"] = dict(frames=int(ids.numel()), **row)
     PB.polar_set_scl_ranking(0)
     return res

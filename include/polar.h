@@ -326,13 +326,18 @@ polar_status polar_workspace_size(const polar_code* code, int64_t B, int32_t L,
 polar_status polar_set_scl_lds_budget(int64_t bytes);
 int64_t polar_get_scl_lds_budget(void);
 
-/* How the list decoder picks the L survivors among the 2L candidates (Sec.
- * II-A describes both): 1 the pruned pseudo sort -- each candidate counts the
- * candidates before it; 2 a bitonic sort of the candidates across the
- * wavefront (list sizes 8 and 32, N >= 32; other lists use the pseudo sort);
- * 0 (default) automatic: the bitonic sort for L = 32, where it measured faster
- * on MI355X, the pseudo sort otherwise.  Both use the strict order (metric,
- * parent position, bit), so results are identical.  Process-wide; host only. */
+/* How the list decoder finds the L survivors among the 2L candidates of a
+ * branching bit (Sec. II-A describes the first two): 1 the pruned pseudo sort
+ * -- each candidate counts the candidates before it; 2 a bitonic sort of the
+ * candidates across the wavefront (list sizes 8 and 32, N >= 32); 3 threshold
+ * selection -- the L-th smallest metric found bit by bit with wavefront
+ * ballots (list sizes 8, 16 and 32, N >= 32); other lists use the pseudo
+ * sort.  0 (default) automatic: the bitonic sort for L = 32, where it
+ * measured fastest on MI355X, the pseudo sort otherwise.  All decide
+ * survival by the strict order (metric, parent position, bit) and keep the
+ * survivors in the order the candidates are listed (parent position, then
+ * bit), so results are identical.  Process-wide; host only; mode outside 0..3
+ * gives POLAR_ERR_INVALID_ARG. */
 polar_status polar_set_scl_ranking(int32_t mode);
 int32_t polar_get_scl_ranking(void);
 

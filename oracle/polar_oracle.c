@@ -469,10 +469,13 @@ void orc_sc_frame(const float* llr, int N, const uint8_t* frozen, int rule, uint
 /*   rule 0: pen(lam, b) = |lam| if b differs from the hard decision, else 0; */
 /*   rule 1: pen(lam, b) = ln(1 + e^{-(1-2b) lam}).                            */
 /* Frozen bit: no branching, bit 0, metric += pen(lam, 0).                    */
-/* Info bit: every path spawns bits 0 and 1; the candidates are ordered by    */
-/* (metric, parent's position in the list, bit) and the first min(L, 2*len)   */
-/* survive, in that order (the "L smallest metrics" of the pruned sort, made  */
-/* a strict total order so that exactly min(L, 2*len) survive).               */
+/* Info bit: every path spawns bits 0 and 1, listed parent by parent (the     */
+/* parent's position in the list, then bit 0 before bit 1).  The candidates   */
+/* ranked first by (metric, parent's position, bit), min(L, 2*len) of them,   */
+/* survive: the "L smallest metrics" of the pruned pseudo sort, made a strict */
+/* total order so that exactly that many survive.  The pseudo sort discards   */
+/* candidates without moving the others, so the survivors form the new list   */
+/* in the order in which the candidates were listed.                          */
 /* End: the path of smallest (metric, position) whose CRC holds; if none      */
 /* holds, the path of smallest (metric, position), reported with crc_ok = 0.  */
 /* ------------------------------------------------------------------------ */
@@ -495,6 +498,14 @@ static int cand_cmp(const void* pa, const void* pb) {
     const scl_cand* b = (const scl_cand*)pb;
     if (a->metric < b->metric) return -1;
     if (a->metric > b->metric) return 1;
+    if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
+    return a->bit - b->bit;
+}
+
+/* the order in which the candidates are listed: parent's position, then bit */
+static int cand_list_cmp(const void* pa, const void* pb) {
+    const scl_cand* a = (const scl_cand*)pa;
+    const scl_cand* b = (const scl_cand*)pb;
     if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
     return a->bit - b->bit;
 }
@@ -602,6 +613,8 @@ int orc_scl_frame(const float* llr, int N, const uint8_t* frozen, const uint8_t*
                 }
             qsort(cand, nc, sizeof(scl_cand), cand_cmp);
             int keep = nc < L ? nc : L;
+            /* the survivors, back in the order they were listed */
+            qsort(cand, keep, sizeof(scl_cand), cand_list_cmp);
             for (int q = 0; q < keep; q++) {
                 path_copy(&nxt[q], &cur[cand[q].parent], N);
                 nxt[q].u[i] = (uint8_t)cand[q].bit;

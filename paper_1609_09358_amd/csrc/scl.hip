@@ -20,10 +20,15 @@
 // decides, and folds the decided bit into the partial sums held in registers.
 // A branching path is copied by pulling from the parent's lane exactly the
 // registers that later bits of the block still read, plus the two pointer
-// vectors.  Survivors are chosen by rank among the 2L candidates under the
-// order (metric, parent list position, bit) -- the pruned pseudo sort of
-// Sec. II-A with a strict tie rule -- and a survivor's slot is its rank, so
-// slot index and list position coincide.  The CRC is tracked per path as a
+// vectors.  The candidates of a branching bit are listed parent by parent
+// (bit 0 first); the L smallest under the strict order (metric, parent list
+// position, bit) survive -- the pruned pseudo sort of Sec. II-A with a strict
+// tie rule -- and keep that candidate order, so a survivor's slot is the
+// number of survivors listed before it (found with a wavefront ballot) and
+// slot index and list position coincide.  Which candidates survive is found
+// by counting (each candidate counts the smaller ones), a bitonic sort across
+// the wavefront, or threshold selection (the L-th smallest metric found bit by
+// bit with ballots).  The CRC is tracked per path as a
 // running syndrome (linear in the decided bits); the decoded bits of the
 // chosen path are recovered from a per-information-bit trace of
 // (parent, bit).
@@ -195,8 +200,8 @@ __device__ __forceinline__ void key_pair(uint32_t lo, uint32_t hi, uint64_t& a, 
 }
 
 // compare-exchange at distance J inside sorted runs of 2K: the lane keeps the
-// smaller key of {a, b} or the larger, by its position (keys are distinct
-// except the padding ones, which are equal, so taking b on a tie is harmless)
+// smaller key of {a, b} or the larger, by its position (keys are distinct:
+// every one carries its lane)
 template <int K, int J>
 __device__ __forceinline__ void bitonic_step(uint32_t& lo, uint32_t& hi, int lane) {
     uint64_t a, b;
@@ -214,11 +219,77 @@ __device__ __forceinline__ void bitonic_merge_all(uint32_t& lo, uint32_t& hi, in
     if constexpr (K < 64) bitonic_merge_all<K * 2>(lo, hi, lane);
 }
 
+// lane p receives the lane of the candidate of rank p; lanes without a
+// candidate sort last (their keys are distinct too, so the result is a
+// permutation of the lanes)
 __device__ __forceinline__ int bitonic_select(float met, int ncand, int lane) {
     uint32_t hi = lane < ncand ? __float_as_uint(met) : 0xFFFFFFFFu;
-    uint32_t lo = lane < ncand ? (uint32_t)lane : 0xFFFFFFFFu;
+    uint32_t lo = (uint32_t)lane;
     bitonic_merge_all<2>(lo, hi, lane);
     return (int)(lo & 63u);
+}
+
+// set bits of a wavefront mask, counted in two 32-bit halves (a uniform
+// 32-bit count keeps the comparisons that use it in scalar instructions)
+__device__ __forceinline__ uint32_t mask_count(uint64_t m) {
+    return (uint32_t)__builtin_popcount((uint32_t)m) + (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+}
+
+// set bits of a wavefront mask below this lane
+__device__ __forceinline__ int mask_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Threshold selection: whether this lane's candidate is among the L smallest
+// of the ncand > L candidates under (metric, lane).  The L-th smallest metric
+// tau is found bit by bit from the top (metrics are non-negative, so their
+// bit patterns order them): the largest value with fewer than L metrics
+// below it.  Candidates below tau survive, and of those equal to tau the
+// lowest lanes, as many as are still missing.  One compare per bit in VALU;
+// the counts are scalar.
+template <int L>
+__device__ __forceinline__ bool threshold_keep(float met, int ncand, int lane) {
+    const uint32_t key = lane < ncand ? __float_as_uint(met) : 0xFFFFFFFFu;
+    uint32_t tau = 0u;
+#pragma unroll
+    for (int b = 30; b >= 0; --b) {
+        const uint32_t trial = tau | (1u << b);
+        tau = mask_count(__ballot(key < trial)) < (uint32_t)L ? trial : tau;
+    }
+    const int need = L - (int)mask_count(__ballot(key < tau));
+    const uint64_t eq = __ballot(key == tau);
+    return key < tau || (key == tau && mask_below(eq) < need);
+}
+
+// ranking of the candidates: the pruned pseudo sort (each candidate counts
+// those before it), a bitonic sort, or threshold selection
+enum : int { kRankCount = 0, kRankBitonic = 1, kRankThreshold = 2 };
+
+// The survivors of one branching bit.  Lane c holds candidate c (parent
+// c >> 1 of the list, bit c & 1) with metric met, c < ncand.  Which
+// candidates survive follows the strict order (metric, parent, bit); the
+// survivors keep the candidate order, so the new list's slot s holds the s-th
+// surviving candidate.  Returns, for lane s, the lane of that candidate
+// (lanes past the new list size get a discarded candidate, whose state no one
+// reads).
+template <int L, int RANK>
+__device__ __forceinline__ int select_survivors(uint32_t* mets, float met, int ncand, int lane) {
+    if (ncand <= L) return lane;  // every candidate survives in place
+    bool keep;
+    if constexpr (RANK == kRankCount) {
+        keep = lane < ncand && candidate_rank<L>(mets, ncand, met, lane) < L;
+    } else if constexpr (RANK == kRankBitonic) {
+        // lane p holds the candidate of rank p and tells it whether p < L
+        const int c = bitonic_select(met, ncand, lane);
+        keep = __builtin_amdgcn_ds_permute(c << 2, lane < L ? 1 : 0) != 0;
+    } else {
+        keep = threshold_keep<L>(met, ncand, lane);
+    }
+    // exactly L survivors: they go to slots 0..L-1 in lane order, the others
+    // to L..63, so the push below has distinct destinations
+    const uint64_t m = __ballot(keep);
+    const int dest = keep ? mask_below(m) : L + mask_below(~m);
+    return __builtin_amdgcn_ds_permute(dest << 2, lane);
 }
 
 struct Layout {
@@ -233,7 +304,7 @@ struct Layout {
     int64_t u_stride;  // u_hat row stride of a ragged batch
 };
 
-template <int L, int BL, bool BITONIC = false>
+template <int L, int BL, int RANK = kRankCount>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code_in, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
                                                  const int32_t* __restrict__ count_dev, int64_t count_host,
@@ -427,16 +498,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     const float pen = (b != (lp < 0.0f ? 1 : 0)) ? fabsf(lp) : 0.0f;
                     const float met = pmp + pen;
                     const int nact = ncand < L ? ncand : L;
-                    int c;
-                    if constexpr (BITONIC) {
-                        c = bitonic_select(met, ncand, lane);
-                    } else {
-                        const int rank = candidate_rank<L>(mets, ncand, met, lane);
-                        // each candidate pushes its lane to the lane of its rank (ranks
-                        // are distinct; lanes without a candidate push to themselves,
-                        // above every rank), so lane l receives the candidate of rank l
-                        c = __builtin_amdgcn_ds_permute((lane < ncand ? rank : lane) << 2, lane);
-                    }
+                    const int c = select_survivors<L, RANK>(mets, met, ncand, lane);
                     const int par = c >> 1;
                     const uint32_t cb = (uint32_t)(c & 1);
                     const uint32_t syn_i = code.syn[i];
@@ -559,12 +621,19 @@ KernelFn pick_bl(int bl) {
     }
 }
 
-// bitonic ranking: instantiated for the list sizes the comparisons use, BL = 5
-KernelFn pick(int L, int n, bool bitonic = false) {
+// the bitonic sort is instantiated for the list sizes the comparisons use and
+// threshold selection for the larger lists, both with BL = 5; the counting
+// rank serves every list
+KernelFn pick(int L, int n, int rank) {
     const int bl = n < 5 ? n : 5;
-    if (bitonic && bl == 5) {
-        if (L == 8) return &scl_kernel<8, 5, true>;
-        if (L == 32) return &scl_kernel<32, 5, true>;
+    if (rank == kRankBitonic && bl == 5) {
+        if (L == 8) return &scl_kernel<8, 5, kRankBitonic>;
+        if (L == 32) return &scl_kernel<32, 5, kRankBitonic>;
+    }
+    if (rank == kRankThreshold && bl == 5) {
+        if (L == 8) return &scl_kernel<8, 5, kRankThreshold>;
+        if (L == 16) return &scl_kernel<16, 5, kRankThreshold>;
+        if (L == 32) return &scl_kernel<32, 5, kRankThreshold>;
     }
     switch (L) {
         case 1: return pick_bl<1>(bl);
@@ -616,13 +685,18 @@ LdsPlan lds_plan(int L, int N, int n, int k, int gl, bool tg) {
 
 }  // namespace scl
 
-// candidate ranking: 0 automatic (the bitonic sort where it measured faster:
-// L = 32), 1 pruned pseudo sort (counting), 2 bitonic sort
+// candidate ranking: 0 automatic (the bitonic sort for L = 32, where it
+// measured fastest on MI355X; the counting rank below), 1 pruned pseudo sort
+// (counting), 2 bitonic sort, 3 threshold selection
 static std::atomic<int> g_scl_rank_mode{0};
 
-static bool use_bitonic(int L) {
-    const int m = g_scl_rank_mode.load(std::memory_order_relaxed);
-    return m == 2 || (m == 0 && L == 32);
+static int rank_kind(int L) {
+    switch (g_scl_rank_mode.load(std::memory_order_relaxed)) {
+        case 1: return scl::kRankCount;
+        case 2: return scl::kRankBitonic;
+        case 3: return scl::kRankThreshold;
+        default: return L == 32 ? scl::kRankBitonic : scl::kRankCount;
+    }
 }
 
 // LDS per workgroup; 0 (automatic) divides a CU's 160 KB among as many
@@ -636,7 +710,7 @@ polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan
 
 polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* plan) {
     const int N = 1 << n;
-    scl::KernelFn fn = scl::pick(L, n, use_bitonic(L));
+    scl::KernelFn fn = scl::pick(L, n, rank_kind(L));
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
     const int gl_min = n < 6 ? n : 6;
     // everything in LDS if it fits; otherwise the trace goes to the global
@@ -680,7 +754,7 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
                         const int32_t* frame_ids, const int32_t* count_dev, int64_t count_host, uint8_t* u_hat,
                         uint8_t* crc_ok, float* pm, void* glob, hipStream_t stream, const MixedIo* io,
                         int64_t u_stride) {
-    scl::KernelFn fn = scl::pick(L, plan.lay_n, use_bitonic(L));
+    scl::KernelFn fn = scl::pick(L, plan.lay_n, rank_kind(L));
     scl::Layout lay;
     lay.gl = plan.gl;
     lay.sl = scl::slot_floats(plan.lay_n, plan.gl);
@@ -727,7 +801,7 @@ extern "C" polar_status polar_set_scl_lds_budget(int64_t bytes) {
 extern "C" int64_t polar_get_scl_lds_budget(void) { return g_scl_lds_budget.load(std::memory_order_relaxed); }
 
 extern "C" polar_status polar_set_scl_ranking(int32_t mode) {
-    if (mode < 0 || mode > 2) return set_error(POLAR_ERR_INVALID_ARG, "polar_set_scl_ranking: mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return set_error(POLAR_ERR_INVALID_ARG, "polar_set_scl_ranking: mode must be 0..3");
     g_scl_rank_mode.store(mode, std::memory_order_relaxed);
     return ok_status();
 }

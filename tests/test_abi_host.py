@@ -96,10 +96,11 @@ def test_pipeline_bp_occupancy_setter():
 def test_scl_ranking_setter():
     lib = PB.lib()
     assert PB.polar_get_scl_ranking() == 0
-    assert lib.polar_set_scl_ranking(3) == 1
+    assert lib.polar_set_scl_ranking(4) == 1
     assert lib.polar_set_scl_ranking(-1) == 1
-    PB.polar_set_scl_ranking(2)
-    assert PB.polar_get_scl_ranking() == 2
+    for mode in (1, 2, 3):
+        PB.polar_set_scl_ranking(mode)
+        assert PB.polar_get_scl_ranking() == mode
     PB.polar_set_scl_ranking(0)
 
 

@@ -485,13 +485,20 @@ def test_pipelined_hybrid_with_capped_bp_grid(occ):
         PB.polar_set_pipeline_bp_occupancy(0)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("N,K,c,L", [(64, 24, 8, 8), (1024, 512, 24, 32), (2048, 1024, 16, 8), (256, 120, 8, 32)])
-def test_ranking_modes_bit_exact(N, K, c, L, mode):
-    """The bitonic-sort and the pseudo-sort survivor selections both decode
-    exactly as the oracle (same strict order), whichever the default picks."""
+@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("N,K,c,L,quant", [(64, 24, 8, 8, 0), (1024, 512, 24, 32, 0), (2048, 1024, 16, 8, 0),
+                                           (256, 120, 8, 32, 0), (512, 256, 16, 16, 0), (1024, 512, 24, 32, 1),
+                                           (256, 128, 8, 16, 1)])
+def test_ranking_modes_bit_exact(N, K, c, L, quant, mode):
+    """The pseudo-sort, bitonic-sort and threshold survivor selections all
+    decode exactly as the oracle (same strict order, survivors kept in the
+    order they were listed), whichever the default picks.  With quant, the
+    channel LLRs are rounded to multiples of 1/2, so path metrics tie exactly,
+    also at the list boundary, where the tie rule decides."""
     B = 9
     code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, B, seed=17 * N + L)
+    if quant:
+        llr = (np.round(llr * 2.0) / 2.0).astype(np.float32)
     ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32")
     PB.polar_set_scl_ranking(mode)
     try:
