@@ -358,6 +358,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             const uint32_t bmask = BS == 32 ? 0xFFFFFFFFu : ((1u << BS) - 1u);
             const uint32_t fw = (code.frozen_bits[i0 >> 5] >> (i0 & 31)) & bmask;
             const uint32_t dw = (code.da_bits[i0 >> 5] >> (i0 & 31)) & bmask;  // decision-aided
+            // the block's register levels and partial sums are all rewritten
+            // before they are read again (lanes that join the list during the
+            // block pull what they read), so they carry nothing into the block
+            // start and its passes may use their registers
+#pragma unroll
+            for (int e = 0; e < 32; ++e) lv[e] = 0.0f;
+#pragma unroll
+            for (int d = 0; d < 5; ++d) ps[d] = 0u;
             // ---------------- block start: levels top..BL, all lanes together
             if (BL < n) {
                 const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
@@ -366,18 +374,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     const int myp = get_byte(ptrL, d + 1);
                     const int mypp = get_byte(ptrP, d);
                     // units of four consecutive items of one slot (a level has at
-                    // least 32 per slot), two units per lane per pass with all loads
-                    // issued before any use; every lane runs every pass, so the lane
+                    // least 32 per slot), UP units per lane per pass with all loads
+                    // issued before any use (the loads of a level in the global
+                    // slice take a trip through the memory hierarchy, so a pass
+                    // keeps several in flight; the registers of the block's lower
+                    // levels are free here); every lane runs every pass, so the lane
                     // shuffles read active lanes only (units past the end redo unit
                     // 0 and store nothing)
+                    constexpr int UP = 4;
                     const int units = act << (d - 2);
                     const bool psum = d == top && j != 0;
-                    for (int u0 = 0; u0 < units; u0 += 128) {
-                        float a[2][4], b[2][4];
-                        int slot[2], e[2];
-                        bool live[2];
+                    for (int u0 = 0; u0 < units; u0 += 64 * UP) {
+                        float a[UP][4], b[UP][4];
+                        int slot[UP], e[UP];
+                        bool live[UP];
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
+                        for (int h = 0; h < UP; ++h) {
                             const int uu = u0 + 64 * h + lane;
                             live[h] = uu < units;
                             const int it = (live[h] ? uu : 0) << 2;
@@ -399,16 +411,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                                 b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
                             }
                         }
-                        uint32_t w[2] = {0u, 0u};
+                        uint32_t w[UP] = {};
                         if (psum) {
 #pragma unroll
-                            for (int h = 0; h < 2; ++h) {
+                            for (int h = 0; h < UP; ++h) {
                                 const int pss = __shfl(mypp, slot[h], 64);
                                 w[h] = psw[pss * PW + ps_off(d) + (e[h] >> 5)] >> (e[h] & 31);
                             }
                         }
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
+                        for (int h = 0; h < UP; ++h) {
                             float v[4];
 #pragma unroll
                             for (int k = 0; k < 4; ++k)
