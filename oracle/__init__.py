@@ -49,8 +49,8 @@ def _lib(prec: str = "f64"):
         lib.orc_scl_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int, C.c_uint32,
                                       C.c_int, C.c_int, _u8p, _u8p, _f64p]
         lib.orc_hybrid_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int, C.c_int,
-                                         C.c_uint32, C.c_int, C.c_double, C.c_int, _f64p, C.c_int, _u8p,
-                                         _u8p, _i32p]
+                                         C.c_uint32, C.c_int, C.c_int, C.c_double, C.c_int, _f64p, C.c_int,
+                                         _u8p, _u8p, _i32p]
         lib.orc_wbp_grad_frame.restype = C.c_double
         lib.orc_wbp_grad_batch.restype = C.c_double
         lib.orc_wbp_grad_batch.argtypes = [_f32p, C.c_int64, C.c_int, _u8p, _u8p, C.c_int,
@@ -266,9 +266,11 @@ def scl_batch(llr, frozen, L, c=0, poly=0, rule=0, prec="f64", da=None):
     return dict(u_hat=uh, crc_ok=ok, pm=pm)
 
 
-def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, prec="f64", da=None, rule=0):
-    """BP (rule 0 min-sum, 1 exact) with the re-encoding stop, then CA-SCL
-    (min-sum metric) on the frames whose BP verdict is not ok."""
+def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, prec="f64", da=None, rule=0, stop=1):
+    """BP (rule 0 min-sum, 1 exact) with the re-encoding stop (stop 1) or the
+    CRC stop (stop 2), then CA-SCL (min-sum metric) on the frames whose BP
+    verdict is not ok."""
+    assert stop in (1, 2)
     fr = _u8(frozen)
     da = None if da is None else _u8(da)
     N = len(fr)
@@ -282,7 +284,7 @@ def hybrid_batch(llr, frozen, K, c, poly, max_iter, L, llr_max=20.0, W=None, pre
         W = _f64(W)
         assert W.size >= max_iter * 2 * n * N
     _lib(prec).orc_hybrid_batch(_p(llr, _f32p), B, N, _p(fr, _u8p), _p(da, _u8p), K, c, poly, max_iter,
-                                llr_max, int(rule), _p(W, _f64p), L, _p(info, _u8p), _p(used, _u8p),
+                                int(stop), llr_max, int(rule), _p(W, _f64p), L, _p(info, _u8p), _p(used, _u8p),
                                 _p(it, _i32p))
     return dict(info=info, used_scl=used, iters=it)
 

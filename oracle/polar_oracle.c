@@ -666,20 +666,21 @@ void orc_scl_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, co
 
 /* ------------------------------------------------------------------------ */
 /* Hybrid decoder (Sec. III): BP with at most max_iter iterations and the    */
-/* re-encoding stop; if BP does not end with a valid CRC, the frame is        */
-/* decoded again by CA-SCL from the channel LLRs.  info_out gets the K info   */
-/* bits of whichever result is kept.  bp_rule selects the BP update rule      */
-/* (0 min-sum, 1 the exact rule of Sec. II-B); the list decoder keeps the     */
-/* min-sum metric.                                                            */
+/* early stop of Sec. II-B -- stop 1 the re-encoding check, stop 2 the CRC,   */
+/* which the paper allows in its place; if BP does not end with a valid CRC,  */
+/* the frame is decoded again by CA-SCL from the channel LLRs.  info_out gets */
+/* the K info bits of whichever result is kept.  bp_rule selects the BP       */
+/* update rule (0 min-sum, 1 the exact rule of Sec. II-B); the list decoder   */
+/* keeps the min-sum metric.                                                  */
 /* ------------------------------------------------------------------------ */
 
 void orc_hybrid_batch(const float* llr, int64_t B, int N, const uint8_t* frozen, const uint8_t* da,
-                      int K, int c, uint32_t poly, int max_iter, double llr_max, int bp_rule, const double* W,
-                      int L, uint8_t* info_out, uint8_t* used_scl, int32_t* iters) {
+                      int K, int c, uint32_t poly, int max_iter, int stop, double llr_max, int bp_rule,
+                      const double* W, int L, uint8_t* info_out, uint8_t* used_scl, int32_t* iters) {
     uint8_t* u = (uint8_t*)malloc(N);
     for (int64_t f = 0; f < B; f++) {
         uint8_t ok = 0, cok = 0;
-        int it = orc_bp_frame(llr + f * N, N, frozen, c, poly, max_iter, 1, llr_max, bp_rule, W, u,
+        int it = orc_bp_frame(llr + f * N, N, frozen, c, poly, max_iter, stop, llr_max, bp_rule, W, u,
                               NULL, NULL, &ok, NULL);
         if (iters) iters[f] = it;
         used_scl[f] = (uint8_t)(ok ? 0 : 1);

@@ -174,7 +174,7 @@ def bp_cost(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, T: int, fail
     return float(o["iters"].float().mean()) + fail_weight * (1.0 - float(o["ok"].float().mean()))
 
 
-def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stage: bool = False):
+def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stage: bool = False, stop: int = 1):
     """Normalized min-sum: the single weight alpha (every g term scaled by it)
     with the fewest BP failures on the frames `llr`; returns (W, alpha, rate)
     with W of shape [T][2][n][N], or [T][2][n] (one weight per stage column)."""
@@ -183,14 +183,14 @@ def fit_scale(code: PB.PolarCode, llr: torch.Tensor, T: int, grid=None, per_stag
     best = None
     for a in grid:
         W = torch.full(shape, float(a), dtype=torch.float32, device=llr.device)
-        r = bp_fail_rate(code, llr, W, T)
+        r = bp_fail_rate(code, llr, W, T, stop=stop)
         if best is None or r < best[2]:
             best = (W, float(a), r)
     return best
 
 
 def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factors=(0.96, 0.98, 1.02, 1.04),
-                  sweeps: int = 1, per_column: bool = False, fail_weight=None, wmax=None):
+                  sweeps: int = 1, per_column: bool = False, fail_weight=None, wmax=None, stop: int = 1):
     """Coordinate search on the BP failure rate itself (or, with fail_weight,
     on bp_cost): each block of weights -- one iteration and sweep direction,
     or (per_column) one iteration, direction and stage column -- in turn is
@@ -199,7 +199,7 @@ def refine_blocks(code: PB.PolarCode, llr: torch.Tensor, W: torch.Tensor, factor
     never amplifies a check-node message, and the per-stage kernel then skips
     the clips that cannot act).  Returns (W, objective)."""
     T = W.shape[0]
-    obj = (lambda w: bp_fail_rate(code, llr, w, T)) if fail_weight is None else \
+    obj = (lambda w: bp_fail_rate(code, llr, w, T, stop=stop)) if fail_weight is None else \
           (lambda w: bp_cost(code, llr, w, T, fail_weight))
     cur = obj(W)
     blocks = [(t, d, s) for t in range(T) for d in range(2) for s in range(code.n)] if per_column else \

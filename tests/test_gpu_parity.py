@@ -295,6 +295,7 @@ def test_scl_frame_subset_scatters_rows():
 
 # ------------------------------------------------------------------ hybrid
 
+@pytest.mark.parametrize("stop", [1, 2])
 @pytest.mark.parametrize("N,K,c,L,design,ebn0,max_iter", [
     (64, 24, 8, 4, 2.0, 1.0, 30),
     (512, 256, 16, 8, 2.5, 1.5, 40),
@@ -302,12 +303,15 @@ def test_scl_frame_subset_scatters_rows():
     (1024, 512, 16, 8, 2.5, 1.5, 200),
     (1024, 512, 24, 32, 2.5, 1.5, 20),
 ])
-def test_hybrid_bit_exact_vs_f32_oracle(N, K, c, L, design, ebn0, max_iter):
+def test_hybrid_bit_exact_vs_f32_oracle(N, K, c, L, design, ebn0, max_iter, stop):
+    """Hybrid with the re-encoding stop or the CRC stop (Sec. II-B allows the
+    CRC in its place): hand-off, information bits, statistics and iteration
+    sum against the oracle's float build."""
     B = 48
     code, info, u, x, llr = frames(N, K, c, design, ebn0, B, seed=N + L)
-    ref = O.hybrid_batch(llr, code.frozen, K, c, POLY[c], max_iter, L, prec="f32")
+    ref = O.hybrid_batch(llr, code.frozen, K, c, POLY[c], max_iter, L, prec="f32", stop=stop)
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
-    dec = PB.HybridDecoder(code, max_iter=max_iter, L=L)
+    dec = PB.HybridDecoder(code, max_iter=max_iter, L=L, stop=stop)
     out = dec(dev(llr), stats=stats)
     assert np.array_equal(host(out["used_scl"]), ref["used_scl"])
     assert np.array_equal(host(out["info"]), ref["info"])
@@ -532,9 +536,9 @@ def test_plain_bp_c1_configuration_bit_exact():
 def test_learned_hybrid_full_size_pipelined_sampled():
     """The benchmark's learned hybrid at its full size and launch path: 65536
     frames at 2.5 dB through the two-stream pipeline, weighted BP T = 20 with one
-    weight per stage column, CA-SCL L = 32 with 320 decision-aided positions,
-    CRC-24; sampled frames (list-decoded ones included) against the oracle's
-    float build with the same weights."""
+    weight per stage column and the CRC stop, CA-SCL L = 32 with 320
+    decision-aided positions, CRC-24; sampled frames (list-decoded ones
+    included) against the oracle's float build with the same weights."""
     N, K, c, L, T, B = 1024, 512, 24, 32, 20, 65536
     code = PB.PolarCode(N, K, c, 0, 2.5, da_bits=320)
     info = inputs.info_bits(B, K, seed=2025)
@@ -544,7 +548,7 @@ def test_learned_hybrid_full_size_pipelined_sampled():
     rng = np.random.default_rng(3)
     Ws = (0.94 * rng.uniform(0.97, 1.03, (T, 2, 10))).astype(np.float32)
     W = dev(Ws)
-    pipe = PB.HybridPipeline(code, max_iter=T, L=L, weights=W)
+    pipe = PB.HybridPipeline(code, max_iter=T, L=L, stop=2, weights=W)
     outs = pipe([llr, llr], want_used=True)
     torch.cuda.synchronize()
     a, b = host(outs[0]["info"]), host(outs[1]["info"])
@@ -554,7 +558,8 @@ def test_learned_hybrid_full_size_pipelined_sampled():
                            rng.choice(B, size=36, replace=False)])
     llr_s = host(llr[torch.from_numpy(pick).cuda()])
     Wn = np.repeat(Ws[..., None], N, axis=3).astype(np.float64)
-    ref = O.hybrid_batch(llr_s, code.frozen, K, c, POLY[c], T, L, W=Wn, prec="f32", da=code.decision_aided)
+    ref = O.hybrid_batch(llr_s, code.frozen, K, c, POLY[c], T, L, W=Wn, prec="f32", da=code.decision_aided,
+                         stop=2)
     assert np.array_equal(a[pick], ref["info"])
     assert np.array_equal(used[pick], ref["used_scl"])
     assert 0.005 < used.mean() < 0.2

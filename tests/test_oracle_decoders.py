@@ -370,12 +370,16 @@ def test_scl_fer_not_worse_than_sc():
 
 # ------------------------------------------------------------------ hybrid
 
+@pytest.mark.parametrize("stop", [1, 2])
 @pytest.mark.parametrize("rule", [0, 1])
-def test_hybrid_is_bp_else_scl(rule):
+def test_hybrid_is_bp_else_scl(rule, stop):
+    """Hybrid of Sec. III, frame by frame: BP's information bits where BP ends
+    with its verdict ok (re-encoding stop, or the CRC stop that Sec. II-B
+    allows in its place), the list decoder's elsewhere."""
     N, K, c, poly, L = 256, 120, 8, 0x07, 4
     fr, info, u, x, llr = _frame(N, K, c, poly, 1.5, seed=51, B=24)
-    h = O.hybrid_batch(llr, fr, K, c, poly, max_iter=40, L=L, rule=rule)
-    bp = O.bp_batch(llr, fr, c, poly, max_iter=40, stop=1, rule=rule)
+    h = O.hybrid_batch(llr, fr, K, c, poly, max_iter=40, L=L, rule=rule, stop=stop)
+    bp = O.bp_batch(llr, fr, c, poly, max_iter=40, stop=stop, rule=rule)
     sl = O.scl_batch(llr, fr, L, c, poly)
     free = np.where(fr == 0)[0]
     assert 0 < h["used_scl"].sum() < 24
