@@ -118,8 +118,7 @@ int bp_list_variants(int n, int32_t* ids, int cap);
 struct SclPlan {
     int gl;              // LLR levels >= gl live in the global slice
     size_t lds_bytes;    // dynamic LDS per workgroup
-    int trace_glob;      // 1: the per-bit trace lives in the global slice
-    int trace_chunk;     // information bits per read-back chunk when trace_glob
+    int trace_glob;      // 1: the per-block trace lives in the global slice
     int tb_off;          // LDS byte offset of the trace when !trace_glob
     size_t trace_off;    // byte offset of the trace inside the global slice
     size_t glob_per_wg;  // global slice bytes per workgroup (levels >= gl, trace)
@@ -127,8 +126,8 @@ struct SclPlan {
     int lay_n;           // log2 of the largest block length the layout holds
 };
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan);
-// a plan that holds any code with n <= max_n (n >= 5) and k <= max_k
-polar_status scl_plan_dims(int max_n, int max_k, int L, int64_t max_frames, SclPlan* plan);
+// a plan that holds any code with n <= max_n (n >= 5)
+polar_status scl_plan_dims(int max_n, int L, int64_t max_frames, SclPlan* plan);
 // io (optional): LLR rows of a ragged batch (frame f at element io->off[f]),
 // u_hat rows then at f * u_stride
 polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float* llr, int L,

@@ -9,7 +9,7 @@
 // device) decoding every frame with its own code and appends the frames whose
 // verdict is not ok to the group's queue, and a persistent CA-SCL kernel
 // drains that queue, again with each frame's own code (its layout holds the
-// group's largest information set).  After the branches join, a merge kernel
+// group's largest block length).  After the branches join, a merge kernel
 // writes every frame's information bits, its list-decoder flag and the
 // statistics.  (Codes shorter than 32 bits form one group each.)  No host round trip and no per-call
 // allocation: the plan owns its workspace.  Because the kernels read the
@@ -194,12 +194,10 @@ extern "C" polar_status polar_mixed_create(const polar_code* const* codes, int32
         const int c = m->rep[g];
         bp_params p = *params;
         p.variant = variants ? variants[c] : 0;
-        int grid = 0, max_k = 0;
-        for (int c2 = 0; c2 < n_codes; ++c2)
-            if (gmap[c2] == g && codes[c2]->k > max_k) max_k = codes[c2]->k;
+        int grid = 0;
         SclPlan sp;
         if ((st = bp_gather_grid(codes[c], &p, max_frames, &grid)) != POLAR_OK ||
-            (st = scl_plan_dims(codes[c]->n, max_k, L, max_frames, &sp)) != POLAR_OK) {
+            (st = scl_plan_dims(codes[c]->n, L, max_frames, &sp)) != POLAR_OK) {
             mixed_release(m);
             return st;
         }

@@ -29,16 +29,18 @@
 // by counting (each candidate counts the smaller ones), a bitonic sort across
 // the wavefront, or threshold selection (the L-th smallest metric found bit by
 // bit with ballots).  The CRC is tracked per path as a
-// running syndrome (linear in the decided bits); the decoded bits of the
-// chosen path are recovered from a per-information-bit trace of
-// (parent, bit).
+// running syndrome (linear in the decided bits).  Each path carries its
+// decided bits of the current block in a register word and the slot it held
+// at the block start (both pulled from the parent on a branch); at every
+// block end each path writes that pair to the trace, so the chosen path is
+// recovered by one step per block (its slot at each block end), after which
+// every lane writes its outputs from the block words.
 //
 // A frame's decode is a long chain of dependent steps, so throughput comes
 // from many frames in flight: the kernel is held to 128 VGPRs (four waves per
 // SIMD) and the LDS state is sized to let sixteen one-wave workgroups share a
 // CU.  What does not fit moves to the workgroup's global slice: first the
-// trace (written once per information bit, read back in chunks for the
-// traceback), then the largest tree levels.
+// trace (5 bytes per block and path), then the largest tree levels.
 #include <atomic>
 #include <type_traits>
 
@@ -297,10 +299,10 @@ struct Layout {
     int sl;      // LDS floats per slot: levels BL..gl-1, level d at offset 2^d - 2^BL, padded
     int pw;      // partial-sum words per slot (levels >= 5)
     int tg;      // 1: the trace lives in the global slice and is read back in chunks
-    int tchunk;  // information bits per chunk of the read-back trace
     int64_t gbytes;  // bytes of the global slice per workgroup
     int64_t toff;    // byte offset of the trace inside the slice
-    int tboff;       // byte offset of the LDS trace (at least N: dec[] sits below it)
+    int tboff;       // byte offset of the LDS trace (the traceback's block chain sits below it)
+    int nblk;        // blocks of the largest block length the layout holds (trace rows)
     int64_t u_stride;  // u_hat row stride of a ragged batch
 };
 
@@ -319,12 +321,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     float* slam = reinterpret_cast<float*>(sm);                   // [L][SL]
     uint32_t* psw = reinterpret_cast<uint32_t*>(slam + L * SL);   // [L][PW]
     uint32_t* mets = psw + L * PW;                                // [64]
-    uint8_t* tbk = sm + lay.tboff;                                // [k][L] unless tg
-    uint8_t* dec = reinterpret_cast<uint8_t*>(slam);              // [N], reuses the LLR area at the end
+    int* chain = reinterpret_cast<int*>(sm);                      // [nblk], reuses the LLR area at the end
 
     unsigned char* gbase = glob_all ? glob_all + (size_t)gid_x() * (size_t)lay.gbytes : nullptr;
     float* glam = reinterpret_cast<float*>(gbase);            // [L][N], levels >= gl
-    uint8_t* tbg = lay.tg ? gbase + lay.toff : nullptr;       // [k][L] when tg
+    // the trace, per block and slot: the block's decided bits (bit r = bit r of
+    // the block) and the slot the path held at the block start; in LDS or, when
+    // tg, in the global slice
+    unsigned char* tbase = lay.tg ? gbase + lay.toff : sm + lay.tboff;
+    uint32_t* tru = reinterpret_cast<uint32_t*>(tbase);               // [nblk][L]
+    uint8_t* tra = tbase + (size_t)lay.nblk * L * sizeof(uint32_t);   // [nblk][L]
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
     const float* const llr_base = mio ? mio->llr : llr;
@@ -351,7 +357,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
         for (int e = 0; e < 32; ++e) lv[e] = 0.0f;
 #pragma unroll
         for (int d = 0; d < 5; ++d) ps[d] = 0u;
-        int infoq = 0;
+        uint32_t ublk = 0u;  // this path's decided bits of the current block
+        int anc = lane;      // the slot this path held at the block start
 
         for (int j = 0; j < (N >> BL); ++j) {
             const int i0 = j << BL;
@@ -366,6 +373,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             for (int e = 0; e < 32; ++e) lv[e] = 0.0f;
 #pragma unroll
             for (int d = 0; d < 5; ++d) ps[d] = 0u;
+            ublk = 0u;
+            anc = lane;
             // ---------------- block start: levels top..BL, all lanes together
             if (BL < n) {
                 const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
@@ -497,11 +506,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     if (lane < act) {
                         bit = lam0 < 0.0f ? 1u : 0u;
                         SYN ^= bit ? code.syn[i] : 0u;
-                        const uint8_t tv = (uint8_t)(lane | (bit << 7));
-                        if (tbg) tbg[infoq * L + lane] = tv;
-                        else tbk[infoq * L + lane] = tv;
+                        ublk |= bit << r;
                     }
-                    ++infoq;
                 } else {
                     const int ncand = 2 * act;
                     const int p = lane >> 1, b = lane & 1;
@@ -526,14 +532,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     for (int d = 0; d < BL; ++d) ps[d] = __shfl(ps[d], par, 64);
 #pragma unroll
                     for (int e = live_from; e < BS; ++e) lv[e] = __shfl(lv[e], par, 64);
-                    if (lane < nact) {
-                        bit = cb;
-                        const uint8_t tv = (uint8_t)(par | (cb << 7));
-                        if (tbg) tbg[infoq * L + lane] = tv;
-                        else tbk[infoq * L + lane] = tv;
-                    }
+                    anc = __shfl(anc, par, 64);
+                    ublk = __shfl(ublk, par, 64) | (cb << r);
+                    if (lane < nact) bit = cb;
                     act = nact;
-                    ++infoq;
                 }
                 // ---- partial sums: the finished block of 2^t bits becomes level t
                 if constexpr (tb < BL) {
@@ -564,6 +566,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     }
                 }
             });
+            // ---- the block's trace entry of every path
+            if (lane < act) {
+                tru[j * L + lane] = ublk;
+                tra[j * L + lane] = (uint8_t)anc;
+            }
         }
         // ---------------- selection: smallest (CRC fails, metric, position)
         uint64_t key = ~0ull;
@@ -576,42 +583,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
         const int best = (int)(key & 0xFF);
         const bool best_ok = ((key >> 40) & 1ull) == 0;
         const float best_pm = __shfl(PM, best, 64);
-        wave_mem_order();
-        for (int it = lane; it < N; it += 64) dec[it] = 0;
-        wave_mem_order();
-        // ---------------- trace the chosen path back through the information bits
-        if (!tbg) {
-            if (lane == 0) {
-                int s = best;
-                for (int qq = infoq - 1; qq >= 0; --qq) {
-                    const uint8_t e = tbk[qq * L + s];
-                    dec[code.info_pos[qq]] = e >> 7;
-                    s = e & 0x7F;
-                }
-            }
-        } else {
-            // chunks of the global trace, last first, staged behind dec[] in LDS
-            uint8_t* ch = dec + ((N + 15) & ~15);
-            const int C = lay.tchunk;
+        // ---------------- trace the chosen path back, one block at a time: the
+        // slot it held at each block's end, then every bit from its block's word
+        // (frozen bits are 0 there)
+        if (lay.tg) wg_mem_order();
+        else wave_mem_order();
+        if (lane == 0) {
             int s = best;
-            wg_mem_order();
-            for (int q1 = infoq; q1 > 0; q1 -= C) {
-                const int q0 = q1 > C ? q1 - C : 0;
-                const int nb = (q1 - q0) * L;
-                for (int it = lane; it < nb; it += 64) ch[it] = tbg[(size_t)q0 * L + it];
-                wave_mem_order();
-                if (lane == 0) {
-                    for (int qq = q1 - 1; qq >= q0; --qq) {
-                        const uint8_t e = ch[(qq - q0) * L + s];
-                        dec[code.info_pos[qq]] = e >> 7;
-                        s = e & 0x7F;
-                    }
-                }
-                wave_mem_order();
+            for (int jj = (N >> BL) - 1; jj >= 0; --jj) {
+                chain[jj] = s;
+                s = tra[jj * L + s];
             }
         }
         wave_mem_order();
-        for (int it = lane; it < N; it += 64) u_hat[urow + it] = dec[it];
+        uint8_t* const urow_p = u_hat + urow;
+        const bool aligned4 = (reinterpret_cast<uintptr_t>(urow_p) & 3u) == 0;
+        for (int it = 4 * lane; it < N; it += 256) {
+            const int jj = it >> BL;
+            const uint32_t w = tru[jj * L + chain[jj]] >> (it & (BS - 1));
+            if (aligned4) {
+                *reinterpret_cast<uint32_t*>(urow_p + it) =
+                    (w & 1u) | ((w & 2u) << 7) | ((w & 4u) << 14) | ((w & 8u) << 21);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) urow_p[it + k] = (uint8_t)((w >> k) & 1u);
+            }
+        }
         if (lane == 0) {
             crc_ok[f] = best_ok ? 1 : 0;
             if (pm_out) pm_out[f] = best_pm;
@@ -666,32 +663,33 @@ int slot_floats(int n, int gl) {
     return (gl > bl ? (1 << gl) - (1 << bl) : 0) + 4;
 }
 
+// bytes of the trace: per block of 2^BL bits and path, the block's decided
+// bits (32-bit word) and the slot the path held at the block start (byte)
+size_t trace_bytes(int L, int N, int n) {
+    const int bl = n < 5 ? n : 5;
+    return (size_t)(N >> bl) * L * 5;
+}
+
 struct LdsPlan {
     size_t bytes;
     int tboff;   // LDS trace offset (tg == 0)
-    int tchunk;  // read-back chunk in information bits (tg == 1)
 };
 
-LdsPlan lds_plan(int L, int N, int n, int k, int gl, bool tg) {
+LdsPlan lds_plan(int L, int N, int n, int gl, bool tg) {
     LdsPlan p{};
+    const int bl = n < 5 ? n : 5;
     size_t b = (size_t)L * slot_floats(n, gl) * 4;  // LLR heap
     b += (size_t)L * ps_words(n) * 4;                // partial sums of levels >= 5
     b += 64 * 4;                                      // candidate metrics
-    const size_t dec_end = align_up((size_t)N, 16);   // dec[] reuses the space from 0
+    // the traceback's block chain reuses the space from 0
+    const size_t chain_end = align_up((size_t)(N >> bl) * 4, 16);
+    b = align_up(b > chain_end ? b : chain_end, 16);
+    p.tboff = 0;
     if (!tg) {
-        b = align_up(b > dec_end ? b : dec_end, 16);
         p.tboff = (int)b;
-        b += (size_t)k * L;                           // trace
-        p.bytes = align_up(b, 16);
-        p.tchunk = 0;
-    } else {
-        const int cmin = k < 64 ? k : 64;
-        const size_t need = dec_end + (size_t)cmin * L;
-        b = align_up(b > need ? b : need, 16);
-        p.bytes = b;
-        p.tboff = 0;
-        p.tchunk = (int)((b - dec_end) / L);
+        b += trace_bytes(L, N, n);
     }
+    p.bytes = align_up(b, 16);
     return p;
 }
 
@@ -717,10 +715,10 @@ static std::atomic<int64_t> g_scl_lds_budget{0};
 constexpr size_t kLdsPerCu = 160 * 1024;
 
 polar_status scl_plan(const polar_code* code, int L, int64_t max_frames, SclPlan* plan) {
-    return scl_plan_dims(code->n, code->k, L, max_frames, plan);
+    return scl_plan_dims(code->n, L, max_frames, plan);
 }
 
-polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* plan) {
+polar_status scl_plan_dims(int n, int L, int64_t max_frames, SclPlan* plan) {
     const int N = 1 << n;
     scl::KernelFn fn = scl::pick(L, n, rank_kind(L));
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
@@ -729,7 +727,7 @@ polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* pla
     // slice first (written once per bit, read once), then the largest levels
     bool tg = false;
     int gl = n;
-    scl::LdsPlan lp = scl::lds_plan(L, N, n, k, gl, tg);
+    scl::LdsPlan lp = scl::lds_plan(L, N, n, gl, tg);
     size_t budget = (size_t)g_scl_lds_budget.load(std::memory_order_relaxed);
     if (budget == 0) {
         int by_regs = 0;
@@ -739,8 +737,8 @@ polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* pla
     }
     if (lp.bytes > budget) {
         tg = true;
-        while (gl > gl_min && scl::lds_plan(L, N, n, k, gl, tg).bytes > budget) --gl;
-        lp = scl::lds_plan(L, N, n, k, gl, tg);
+        while (gl > gl_min && scl::lds_plan(L, N, n, gl, tg).bytes > budget) --gl;
+        lp = scl::lds_plan(L, N, n, gl, tg);
     }
     if (lp.bytes > 160 * 1024) return set_error(POLAR_ERR_UNSUPPORTED, "scl: list too large for LDS");
     int per_cu = 0;
@@ -752,11 +750,10 @@ polar_status scl_plan_dims(int n, int k, int L, int64_t max_frames, SclPlan* pla
     plan->gl = gl;
     plan->lds_bytes = lp.bytes;
     plan->trace_glob = tg ? 1 : 0;
-    plan->trace_chunk = lp.tchunk;
     plan->tb_off = lp.tboff;
     const size_t lam_b = (gl < n) ? (size_t)L * N * 4 : 0;
     plan->trace_off = lam_b;
-    plan->glob_per_wg = align_up(lam_b + (tg ? (size_t)k * L : 0), 256);
+    plan->glob_per_wg = align_up(lam_b + (tg ? scl::trace_bytes(L, N, n) : 0), 256);
     plan->grid = (int)grid;
     plan->lay_n = n;
     return POLAR_OK;
@@ -772,7 +769,7 @@ polar_status launch_scl(const polar_code* code, const SclPlan& plan, const float
     lay.sl = scl::slot_floats(plan.lay_n, plan.gl);
     lay.pw = scl::ps_words(plan.lay_n);
     lay.tg = plan.trace_glob;
-    lay.tchunk = plan.trace_chunk;
+    lay.nblk = (1 << plan.lay_n) >> (plan.lay_n < 5 ? plan.lay_n : 5);
     lay.gbytes = (int64_t)plan.glob_per_wg;
     lay.toff = (int64_t)plan.trace_off;
     lay.tboff = plan.tb_off;
