@@ -260,16 +260,18 @@ def main():
     # with the BP occupancy cap that leaves the list decoder most room (tuned
     # beforehand, untimed)
     from paper_1609_09358_amd import autotune
-    occ = autotune.tune_pipeline_occupancy(learned_pipe, llr)
+    occ = autotune.tune_pipeline(learned_pipe, llr)
     elapsed = run_pipe(learned_pipe, out, args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
     gbps = B * K * args.steps / elapsed / 1e9
     # the same steps on one stream, and the plain hybrid on the same frames
     gbps_single = B * K * args.steps / run_steps(learned, out, args.steps, args.warmup) / 1e9
-    occ_p = autotune.tune_pipeline_occupancy(plain_pipe, llr)
+    occ_p = autotune.tune_pipeline(plain_pipe, llr)
     gbps_plain = B * K * args.steps / run_pipe(plain_pipe, out_p, args.steps, args.warmup) / 1e9
     PB.polar_set_pipeline_bp_occupancy(0)
     gbps_plain_single = B * K * args.steps / run_steps(plain, out_p, args.steps, args.warmup) / 1e9
+    # the learned decoder's list-decoder settings for what follows (kernel timing)
+    PB.polar_set_scl_lds_budget(occ["lds_budget"])
 
     # ---- statistics of one step of each
     def one(dec, o):
@@ -336,7 +338,7 @@ def main():
         "mcnemar_only_plain_wrong": only_p,
         "fer_timed_batch": fer_batch,
         "learned_single_stream_Gbps": round(gbps_single, 4),
-        "pipeline_bp_wgs_per_cu": {"learned": occ, "plain": occ_p},
+        "pipeline_tuning": {"learned": occ, "plain": occ_p},
         "plain_hybrid_Gbps": round(gbps_plain, 4),
         "plain_single_stream_Gbps": round(gbps_plain_single, 4),
         "speedup_vs_plain": round(gbps / gbps_plain, 3),

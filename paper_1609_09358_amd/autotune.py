@@ -156,23 +156,51 @@ def tune_mixed_plan(codes, args, max_iter: int, L: int, variants, budgets=(0, 12
     return {"variants": variants, "budget": best_b, "ms": ms}
 
 
+def _time_pipe(pipe: PB.HybridPipeline, llr: torch.Tensor, steps: int) -> float:
+    """ms per batch of the two-stream hybrid over `steps` batches of `llr`."""
+    import time
+    # two output buffers alternate: consecutive batches of a call must not share one
+    out = [dict(info=torch.empty((llr.shape[0], pipe.code.K), dtype=torch.uint8, device=llr.device)) for _ in range(2)]
+    alt = lambda k: [out[i % 2] for i in range(k)]
+    pipe([llr] * 2, outs=alt(2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipe([llr] * steps, outs=alt(steps))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
 def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=(0, 4, 6, 8), steps: int = 6) -> dict:
     """Time the two-stream hybrid over `steps` batches of `llr` for each cap on
     BP workgroups per CU (polar_set_pipeline_bp_occupancy; 0 = none) and leave
     the fastest set.  Returns {"wgs_per_cu": best, "ms": {cap: ms per batch}}."""
-    import time
     timings = {}
-    # two output buffers alternate: consecutive batches of a call must not share one
-    out = [dict(info=torch.empty((llr.shape[0], pipe.code.K), dtype=torch.uint8, device=llr.device)) for _ in range(2)]
-    alt = lambda k: [out[i % 2] for i in range(k)]
     for c in choices:
         PB.polar_set_pipeline_bp_occupancy(c)
-        pipe([llr] * 2, outs=alt(2))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pipe([llr] * steps, outs=alt(steps))
-        torch.cuda.synchronize()
-        timings[c] = (time.perf_counter() - t0) / steps * 1e3
+        timings[c] = _time_pipe(pipe, llr, steps)
     best = min(timings, key=timings.get)
     PB.polar_set_pipeline_bp_occupancy(best)
     return {"wgs_per_cu": int(best), "ms": {int(k): round(v, 4) for k, v in timings.items()}}
+
+
+def tune_pipeline(pipe: PB.HybridPipeline, llr: torch.Tensor, budgets=(0, 12288, 14336, 16384, 20480),
+                  caps=(0, 4, 6, 8), steps: int = 6) -> dict:
+    """The two-stream hybrid's launch settings: first the list decoder's LDS
+    budget per workgroup (polar_set_scl_lds_budget; 0 = the automatic share,
+    a CU's LDS over the workgroups its registers allow), with no BP cap, then
+    the cap on BP workgroups per CU with the best budget; both timed over
+    `steps` batches of `llr` and left set.  The list decoder's LDS competes
+    with the BP workgroups beside it: a larger budget keeps more of its state
+    (the trace, then tree levels) out of the global slice, a smaller one leaves
+    room for more BP workgroups.  Results are the same for every setting.
+    Returns {"lds_budget": b, "wgs_per_cu": c, "ms_budget": {...}, "ms_cap": {...}}."""
+    PB.polar_set_pipeline_bp_occupancy(0)
+    tb = {}
+    for b in budgets:
+        PB.polar_set_scl_lds_budget(b)
+        tb[b] = _time_pipe(pipe, llr, steps)
+    best_b = min(tb, key=tb.get)
+    PB.polar_set_scl_lds_budget(best_b)
+    occ = tune_pipeline_occupancy(pipe, llr, caps, steps)
+    return {"lds_budget": int(best_b), "wgs_per_cu": occ["wgs_per_cu"],
+            "ms_budget": {int(k): round(v, 4) for k, v in tb.items()}, "ms_cap": occ["ms"]}

@@ -70,6 +70,40 @@ __device__ __forceinline__ void wg_mem_order() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Pointers typed by address space: LDS (3) and global (1).  Generic pointers
+// would compile to flat instructions, whose waits also wait for every
+// outstanding global access, and an LDS access through them takes the slower
+// flat path; so LDS and global data are never reached through one pointer.
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+template <typename T>
+using glb_ptr = __attribute__((address_space(1))) T*;
+
+// plain 4-lane vectors (the HIP vector classes do not bind to pointers of a
+// named address space)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> as_lds(void* p) {
+    return (lds_ptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ glb_ptr<T> as_glb(const void* p) {
+    return (glb_ptr<T>)const_cast<void*>(p);
+}
+
+// a value every lane holds alike, moved to scalar registers (so what is read
+// through it becomes scalar or uniform-address work)
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
 // 16 one-byte entries (slot read at each level) held in two 64-bit registers
 struct PtrVec {
     uint64_t lo, hi;
@@ -127,7 +161,7 @@ __device__ __forceinline__ uint32_t combine(uint32_t bit, const uint32_t (&ps)[5
 // The metrics go through LDS once; each lane then reads them back as uint4
 // broadcasts, four at a time, so the reads overlap.
 template <int L>
-__device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float met, int lane) {
+__device__ __forceinline__ int candidate_rank(lds_ptr<uint32_t> mets, int ncand, float met, int lane) {
     constexpr int NC = 2 * L;
     constexpr int G = NC / 4 < 1 ? 1 : (NC / 4 > 4 ? 4 : NC / 4);  // uint4 reads in flight
     if (lane < ncand) mets[lane] = __float_as_uint(met);
@@ -135,9 +169,9 @@ __device__ __forceinline__ int candidate_rank(uint32_t* mets, int ncand, float m
     const uint32_t mb = __float_as_uint(met);
     int rank = 0;
     for (int c0 = 0; c0 < ncand; c0 += 4 * G) {
-        uint4 v[G];
+        u32x4 v[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = reinterpret_cast<const uint4*>(mets + c0)[g];
+        for (int g = 0; g < G; ++g) v[g] = ((lds_ptr<const u32x4>)(mets + c0))[g];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int c = c0 + 4 * g;
@@ -275,7 +309,7 @@ enum : int { kRankCount = 0, kRankBitonic = 1, kRankThreshold = 2 };
 // (lanes past the new list size get a discarded candidate, whose state no one
 // reads).
 template <int L, int RANK>
-__device__ __forceinline__ int select_survivors(uint32_t* mets, float met, int ncand, int lane) {
+__device__ __forceinline__ int select_survivors(lds_ptr<uint32_t> mets, float met, int ncand, int lane) {
     if (ncand <= L) return lane;  // every candidate survives in place
     bool keep;
     if constexpr (RANK == kRankCount) {
@@ -318,32 +352,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
     const int lane = lid_x();
     const int gl = lay.gl, SL = lay.sl, PW = lay.pw;
 
-    float* slam = reinterpret_cast<float*>(sm);                   // [L][SL]
-    uint32_t* psw = reinterpret_cast<uint32_t*>(slam + L * SL);   // [L][PW]
-    uint32_t* mets = psw + L * PW;                                // [64]
-    int* chain = reinterpret_cast<int*>(sm);                      // [nblk], reuses the LLR area at the end
+    const lds_ptr<float> slam = as_lds<float>(sm);                          // [L][SL]
+    const lds_ptr<uint32_t> psw = (lds_ptr<uint32_t>)(slam + L * SL);       // [L][PW]
+    const lds_ptr<uint32_t> mets = psw + L * PW;                            // [64]
+    const lds_ptr<int> chain = as_lds<int>(sm);                             // [nblk], reuses the LLR area at the end
 
     unsigned char* gbase = glob_all ? glob_all + (size_t)gid_x() * (size_t)lay.gbytes : nullptr;
-    float* glam = reinterpret_cast<float*>(gbase);            // [L][N], levels >= gl
+    const glb_ptr<float> glam = as_glb<float>(gbase);         // [L][N], levels >= gl
     // the trace, per block and slot: the block's decided bits (bit r = bit r of
     // the block) and the slot the path held at the block start; in LDS or, when
     // tg, in the global slice
-    unsigned char* tbase = lay.tg ? gbase + lay.toff : sm + lay.tboff;
-    uint32_t* tru = reinterpret_cast<uint32_t*>(tbase);               // [nblk][L]
-    uint8_t* tra = tbase + (size_t)lay.nblk * L * sizeof(uint32_t);   // [nblk][L]
+    const size_t tra_off = (size_t)lay.nblk * L * sizeof(uint32_t);
+    const lds_ptr<uint32_t> tru_l = as_lds<uint32_t>(sm + lay.tboff);   // [nblk][L]
+    const lds_ptr<uint8_t> tra_l = as_lds<uint8_t>(sm + lay.tboff + tra_off);
+    const glb_ptr<uint32_t> tru_g = as_glb<uint32_t>(gbase + lay.toff);
+    const glb_ptr<uint8_t> tra_g = as_glb<uint8_t>(gbase + lay.toff + tra_off);
+    const bool tg = lay.tg != 0;
 
     const int64_t count = count_dev ? (int64_t)(*count_dev) : count_host;
     const float* const llr_base = mio ? mio->llr : llr;
     const int64_t* const row_off = mio ? mio->off : nullptr;
     for (int64_t q = gid_x(); q < count; q += num_groups_x()) {
-        const int64_t f = frame_ids ? (int64_t)frame_ids[q] : q;
+        const int64_t f = frame_ids ? (int64_t)uniform_int(frame_ids[q]) : q;
         // the frame's code (several codes in one launch: the layout holds the
         // largest; level offsets inside a slot do not depend on n)
-        const CodeDev code = (mio && mio->codes) ? mio->codes[mio->code_of[f]] : code_in;
+        CodeDev code = code_in;
+        if (mio && mio->codes) {
+            code = mio->codes[uniform_int(mio->code_of[f])];
+            code.frozen_bits = uniform_ptr(code.frozen_bits);
+            code.da_bits = uniform_ptr(code.da_bits);
+            code.syn = uniform_ptr(code.syn);
+            code.n = uniform_int(code.n);
+            code.N = uniform_int(code.N);
+        }
         const int n = code.n, N = code.N;
+        // the frame's frozen and decision-aided words, lane w holding word w
+        // (and word 64 + w): a block reads its word from the lanes
+        const int nw = N >= 32 ? N >> 5 : 1;
+        const glb_ptr<const uint32_t> fzb = as_glb<const uint32_t>(code.frozen_bits);
+        const glb_ptr<const uint32_t> dab = as_glb<const uint32_t>(code.da_bits);
+        const uint32_t fzv0 = lane < nw ? fzb[lane] : 0u, fzv1 = 64 + lane < nw ? fzb[64 + lane] : 0u;
+        const uint32_t dav0 = lane < nw ? dab[lane] : 0u, dav1 = 64 + lane < nw ? dab[64 + lane] : 0u;
+        const glb_ptr<const uint32_t> synp = as_glb<const uint32_t>(code.syn);
         // rows of frame f: LLRs at row_off[f] (ragged batch) or f * N; u_hat at
         // f * u_stride (ragged batch) or f * N
-        const float* chan = llr_base + (row_off ? row_off[f] : f * N);
+        const float* const chan_g = llr_base + (row_off ? row_off[f] : f * N);
+        const glb_ptr<const float> chan = as_glb<const float>(chan_g);
+        const bool chan16 = (reinterpret_cast<uintptr_t>(chan_g) & 15u) == 0;  // 16-byte loads possible
         const int64_t urow = f * (row_off ? lay.u_stride : (int64_t)N);
 
         int act = 1;
@@ -363,8 +418,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
         for (int j = 0; j < (N >> BL); ++j) {
             const int i0 = j << BL;
             const uint32_t bmask = BS == 32 ? 0xFFFFFFFFu : ((1u << BS) - 1u);
-            const uint32_t fw = (code.frozen_bits[i0 >> 5] >> (i0 & 31)) & bmask;
-            const uint32_t dw = (code.da_bits[i0 >> 5] >> (i0 & 31)) & bmask;  // decision-aided
+            const int wi = i0 >> 5;
+            const uint32_t fword = (uint32_t)__builtin_amdgcn_readlane((int)(wi < 64 ? fzv0 : fzv1), wi & 63);
+            const uint32_t dword = (uint32_t)__builtin_amdgcn_readlane((int)(wi < 64 ? dav0 : dav1), wi & 63);
+            const uint32_t fw = (fword >> (i0 & 31)) & bmask;
+            const uint32_t dw = (dword >> (i0 & 31)) & bmask;  // decision-aided
+            // the block's CRC syndromes, lane r holding position i0 + r
+            const uint32_t synv = synp[i0 + (lane & (BS - 1))];
             // the block's register levels and partial sums are all rewritten
             // before they are read again (lanes that join the list during the
             // block pull what they read), so they carry nothing into the block
@@ -405,17 +465,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                             slot[h] = it >> d;
                             e[h] = it & (sz - 1);
                             if (d + 1 == n) {
+                                if (chan16) {
+                                    const f32x4 ta = *(glb_ptr<const f32x4>)(chan + e[h]);
+                                    const f32x4 tb = *(glb_ptr<const f32x4>)(chan + e[h] + sz);
+                                    a[h][0] = ta.x; a[h][1] = ta.y; a[h][2] = ta.z; a[h][3] = ta.w;
+                                    b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
+                                } else {
 #pragma unroll
-                                for (int k = 0; k < 4; ++k) {
-                                    a[h][k] = chan[e[h] + k];
-                                    b[h][k] = chan[e[h] + sz + k];
+                                    for (int k = 0; k < 4; ++k) {
+                                        a[h][k] = chan[e[h] + k];
+                                        b[h][k] = chan[e[h] + sz + k];
+                                    }
                                 }
                             } else {
                                 const int src = (d == top) ? __shfl(myp, slot[h], 64) : slot[h];
-                                const float* p = (d + 1 < gl) ? slam + src * SL + ((2 << d) - BS) + e[h]
-                                                              : glam + (size_t)src * N + (2 << d) + e[h];
-                                const float4 ta = *reinterpret_cast<const float4*>(p);
-                                const float4 tb = *reinterpret_cast<const float4*>(p + sz);
+                                f32x4 ta, tb;
+                                if (d + 1 < gl) {
+                                    const lds_ptr<float> p = slam + src * SL + ((2 << d) - BS) + e[h];
+                                    ta = *(lds_ptr<const f32x4>)p;
+                                    tb = *(lds_ptr<const f32x4>)(p + sz);
+                                } else {
+                                    const glb_ptr<float> p = glam + (size_t)src * N + (2 << d) + e[h];
+                                    ta = *(glb_ptr<const f32x4>)p;
+                                    tb = *(glb_ptr<const f32x4>)(p + sz);
+                                }
                                 a[h][0] = ta.x; a[h][1] = ta.y; a[h][2] = ta.z; a[h][3] = ta.w;
                                 b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
                             }
@@ -436,9 +509,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                                 v[k] = psum ? (((w[h] >> k) & 1u) ? b[h][k] - a[h][k] : b[h][k] + a[h][k])
                                             : f_ms(a[h][k], b[h][k]);
                             if (live[h]) {
-                                float* q = (d < gl) ? slam + slot[h] * SL + sz - BS + e[h]
-                                                    : glam + (size_t)slot[h] * N + sz + e[h];
-                                *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
+                                const f32x4 o = {v[0], v[1], v[2], v[3]};
+                                if (d < gl) *(lds_ptr<f32x4>)(slam + slot[h] * SL + sz - BS + e[h]) = o;
+                                else *(glb_ptr<f32x4>)(glam + (size_t)slot[h] * N + sz + e[h]) = o;
                             }
                         }
                     }
@@ -455,7 +528,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                 constexpr int live_from = (r + 1 < BS) ? (2 << ctz_c(r + 1)) : 32;
                 // trailing ones of the bit index (>= BL at the block's last bit)
                 constexpr int tb = (r + 1 < BS) ? ctz_c(~r) : BL;
-                const int i = i0 + r;
 
                 // ---- LLR levels min(top, BL-1)..0 of this lane's path
                 if (lane < act) {
@@ -467,10 +539,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                             for (int e = 0; e < BS; ++e) src[e] = chan[e];
                         } else {
                             const int sl = (r == 0) ? lane : get_byte(ptrL, BL);
-                            const float* p = slam + sl * SL;
+                            const lds_ptr<float> p = slam + sl * SL;
 #pragma unroll
                             for (int e4 = 0; e4 < BS / 4; ++e4) {
-                                const float4 t4 = reinterpret_cast<const float4*>(p)[e4];
+                                const f32x4 t4 = ((lds_ptr<const f32x4>)p)[e4];
                                 src[4 * e4] = t4.x;
                                 src[4 * e4 + 1] = t4.y;
                                 src[4 * e4 + 2] = t4.z;
@@ -505,7 +577,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     // hard decision; no branching, no metric change, same slots
                     if (lane < act) {
                         bit = lam0 < 0.0f ? 1u : 0u;
-                        SYN ^= bit ? code.syn[i] : 0u;
+                        SYN ^= bit ? (uint32_t)__builtin_amdgcn_readlane((int)synv, r) : 0u;
                         ublk |= bit << r;
                     }
                 } else {
@@ -519,7 +591,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     const int c = select_survivors<L, RANK>(mets, met, ncand, lane);
                     const int par = c >> 1;
                     const uint32_t cb = (uint32_t)(c & 1);
-                    const uint32_t syn_i = code.syn[i];
+                    const uint32_t syn_i = (uint32_t)__builtin_amdgcn_readlane((int)synv, r);
                     // pull the parent's state: metric, syndrome, pointers, live registers
                     // (lanes past the new list size pull lane 0's state, which no one reads)
                     PM = __shfl(met, c, 64);
@@ -568,8 +640,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             });
             // ---- the block's trace entry of every path
             if (lane < act) {
-                tru[j * L + lane] = ublk;
-                tra[j * L + lane] = (uint8_t)anc;
+                if (tg) {
+                    tru_g[j * L + lane] = ublk;
+                    tra_g[j * L + lane] = (uint8_t)anc;
+                } else {
+                    tru_l[j * L + lane] = ublk;
+                    tra_l[j * L + lane] = (uint8_t)anc;
+                }
             }
         }
         // ---------------- selection: smallest (CRC fails, metric, position)
@@ -592,17 +669,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             int s = best;
             for (int jj = (N >> BL) - 1; jj >= 0; --jj) {
                 chain[jj] = s;
-                s = tra[jj * L + s];
+                s = tg ? tra_g[jj * L + s] : tra_l[jj * L + s];
             }
         }
         wave_mem_order();
-        uint8_t* const urow_p = u_hat + urow;
-        const bool aligned4 = (reinterpret_cast<uintptr_t>(urow_p) & 3u) == 0;
+        const glb_ptr<uint8_t> urow_p = as_glb<uint8_t>(u_hat + urow);
+        const bool aligned4 = (reinterpret_cast<uintptr_t>(u_hat + urow) & 3u) == 0;
         for (int it = 4 * lane; it < N; it += 256) {
             const int jj = it >> BL;
-            const uint32_t w = tru[jj * L + chain[jj]] >> (it & (BS - 1));
+            const int s = chain[jj];
+            const uint32_t w = (tg ? tru_g[jj * L + s] : tru_l[jj * L + s]) >> (it & (BS - 1));
             if (aligned4) {
-                *reinterpret_cast<uint32_t*>(urow_p + it) =
+                *(glb_ptr<uint32_t>)(urow_p + it) =
                     (w & 1u) | ((w & 2u) << 7) | ((w & 4u) << 14) | ((w & 8u) << 21);
             } else {
 #pragma unroll
