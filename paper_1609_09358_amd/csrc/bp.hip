@@ -68,6 +68,53 @@ __device__ __forceinline__ uint64_t lane_bits(const uint8_t* src, int lane) {
     else return load_bits<G>(src + lane * G::CB);
 }
 
+// Lane exchanges of the stop tests, all in VALU (no LDS round trip, which
+// the early-stop test would otherwise wait on in every iteration):
+// lane ^ 1, ^ 2 by quad permutes; a lane of the other quad of its eight, the
+// other half of its row of sixteen by the half-row and row mirrors (for a
+// reduction any lane of the other half serves); lane ^ 16, ^ 32 by the gfx950
+// row swaps.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+// XOR of s over each group of TL consecutive lanes (TL a power of two <= 64);
+// every lane of the group gets it
+template <int TL>
+__device__ __forceinline__ uint32_t group_xor(uint32_t s) {
+    if constexpr (TL > 1) s ^= dpp32<0xB1>(s);   // quad_perm [1,0,3,2]
+    if constexpr (TL > 2) s ^= dpp32<0x4E>(s);   // quad_perm [2,3,0,1]
+    if constexpr (TL > 4) s ^= dpp32<0x141>(s);  // row_half_mirror
+    if constexpr (TL > 8) s ^= dpp32<0x140>(s);  // row_mirror
+    if constexpr (TL > 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(s, s, false, false);
+        s = r[0] ^ r[1];
+    }
+    if constexpr (TL > 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(s, s, false, false);
+        s = r[0] ^ r[1];
+    }
+    return s;
+}
+
+// the value of lane + Q (Q a power of two <= 32) for the lanes whose bit Q is
+// clear; what the other lanes get is not used.  Row shifts inside a row of
+// sixteen; for 16 and 32 the row swaps, whose second result holds, on those
+// lanes, the partner row
+template <int Q>
+__device__ __forceinline__ uint32_t from_lane_above(uint32_t v) {
+    if constexpr (Q < 16) {
+        // row_shl: lane i reads lane i + Q of its row (lanes past the row's end get 0)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + Q, 0xF, 0xF, false);
+    } else if constexpr (Q == 16) {
+        return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    } else {
+        static_assert(Q == 32, "distance");
+        return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    }
+}
+
 // bits p of a 64-bit word with p & d == 0 (d a power of two)
 constexpr uint64_t low_half_mask(int d) {
     uint64_t m = 0;
@@ -89,11 +136,15 @@ __device__ __forceinline__ bool reencode_check(const uint8_t* ub, const uint8_t*
             u ^= (u >> d) & m;
         }
     });
-#pragma unroll
-    for (int q = 1; q < G::TL; q <<= 1) {
-        uint64_t o = (uint64_t)__shfl_xor((unsigned long long)u, q, 64);
-        if ((lane & q) == 0) u ^= o;
-    }
+    // butterflies across the checker lanes: lanes with bit q clear take lane + q
+    static_for<0, 6>([&](auto QC) {
+        constexpr int q = 1 << decltype(QC)::value;
+        if constexpr (q < G::TL) {
+            const uint32_t lo = from_lane_above<q>((uint32_t)u);
+            const uint32_t hi = G::CB > 32 ? from_lane_above<q>((uint32_t)(u >> 32)) : 0u;
+            if ((lane & q) == 0) u ^= ((uint64_t)hi << 32) | lo;
+        }
+    });
     uint64_t bad = __ballot(u != x);
     if constexpr (G::TL < 64) {
         const int grp = (__lane_id() / G::TL) * G::TL;
@@ -121,9 +172,7 @@ __device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub
         for (int q = 1; q < 4 / G::CB; ++q) nib |= __shfl_xor(part, q, 64);
         s = (sh == 0) ? code.syn_nib[(size_t)g * 16 + (nib & 0xF)] : 0u;
     }
-#pragma unroll
-    for (int q = 1; q < G::TL; q <<= 1) s ^= __shfl_xor(s, q, 64);
-    return s == 0;
+    return group_xor<G::TL>(s) == 0;
 }
 
 // LDS of one workgroup: transpose buffers and the packed-decision staging
