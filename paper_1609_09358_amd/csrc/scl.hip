@@ -184,10 +184,12 @@ __device__ __forceinline__ int candidate_rank(lds_ptr<uint32_t> mets, int ncand,
     return rank;
 }
 
-// Bitonic sort of the candidates across the wavefront (the alternative to the
-// pruned pseudo sort that Sec. II-A also describes): keys (metric bits, lane)
-// in the same strict order as candidate_rank, lanes without a candidate last;
-// after the network lane p holds the key of rank p, i.e. the candidate it takes.
+// Bitonic sorting network over the candidates across the wavefront (the
+// alternative to the pruned pseudo sort that Sec. II-A also describes): keys
+// (metric bits, lane) in the same strict order as candidate_rank, lanes
+// without a candidate last; only the stages that separate the L smallest keys
+// from the rest are run (survivors keep the candidate order, so the order
+// among them is not needed).
 
 // The keys of lane and of lane ^ J, all in VALU: data-parallel-primitive
 // moves inside a row of 16 lanes for J <= 8 (J = 1, 2: one quad permute;
@@ -235,33 +237,48 @@ __device__ __forceinline__ void key_pair(uint32_t lo, uint32_t hi, uint64_t& a, 
     }
 }
 
-// compare-exchange at distance J inside sorted runs of 2K: the lane keeps the
-// smaller key of {a, b} or the larger, by its position (keys are distinct:
-// every one carries its lane)
+// one compare-exchange at distance J while merging runs into sorted runs of
+// K: the lane keeps the smaller key of {a, b} or the larger, by its position
+// (keys are distinct: every one carries its lane)
 template <int K, int J>
-__device__ __forceinline__ void bitonic_step(uint32_t& lo, uint32_t& hi, int lane) {
+__device__ __forceinline__ void bitonic_cx(uint32_t& lo, uint32_t& hi, int lane) {
     uint64_t a, b;
     key_pair<J>(lo, hi, a, b);
     const bool keep_max = ((lane & K) == 0) != ((lane & J) == 0);
     const uint64_t r = ((b < a) != keep_max) ? b : a;
     lo = (uint32_t)r;
     hi = (uint32_t)(r >> 32);
-    if constexpr (J > 1) bitonic_step<K, J / 2>(lo, hi, lane);
 }
 
-template <int K>
-__device__ __forceinline__ void bitonic_merge_all(uint32_t& lo, uint32_t& hi, int lane) {
-    bitonic_step<K, K / 2>(lo, hi, lane);
-    if constexpr (K < 64) bitonic_merge_all<K * 2>(lo, hi, lane);
+// the stages J = K/2 .. 1 that merge bitonic runs into sorted runs of K
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge(uint32_t& lo, uint32_t& hi, int lane) {
+    bitonic_cx<K, J>(lo, hi, lane);
+    if constexpr (J > 1) bitonic_merge<K, J / 2>(lo, hi, lane);
 }
 
-// lane p receives the lane of the candidate of rank p; lanes without a
-// candidate sort last (their keys are distinct too, so the result is a
-// permutation of the lanes)
-__device__ __forceinline__ int bitonic_select(float met, int ncand, int lane) {
+// every merge from runs of 2 up to sorted runs of K_END, in alternating
+// directions
+template <int K, int K_END>
+__device__ __forceinline__ void bitonic_merge_upto(uint32_t& lo, uint32_t& hi, int lane) {
+    bitonic_merge<K, K / 2>(lo, hi, lane);
+    if constexpr (K < K_END) bitonic_merge_upto<K * 2, K_END>(lo, hi, lane);
+}
+
+// The L smallest keys of lanes 0..2L-1 gathered in lanes 0..L-1, in no
+// particular order (lanes without a candidate carry the largest keys): the
+// bitonic sort's merges up to sorted runs of L, which leave lanes 0..2L-1 one
+// bitonic sequence, then the first compare-exchange of the next merge, at
+// distance L, which puts the smaller key of each pair below -- the sort's
+// remaining stages would only order the halves.  Returns the lane of the
+// candidate whose key this lane now holds (the keys stay a permutation of the
+// lanes' own).
+template <int L>
+__device__ __forceinline__ int bitonic_partition(float met, int ncand, int lane) {
     uint32_t hi = lane < ncand ? __float_as_uint(met) : 0xFFFFFFFFu;
     uint32_t lo = (uint32_t)lane;
-    bitonic_merge_all<2>(lo, hi, lane);
+    bitonic_merge_upto<2, L>(lo, hi, lane);
+    bitonic_cx<2 * L, L>(lo, hi, lane);
     return (int)(lo & 63u);
 }
 
@@ -315,8 +332,8 @@ __device__ __forceinline__ int select_survivors(lds_ptr<uint32_t> mets, float me
     if constexpr (RANK == kRankCount) {
         keep = lane < ncand && candidate_rank<L>(mets, ncand, met, lane) < L;
     } else if constexpr (RANK == kRankBitonic) {
-        // lane p holds the candidate of rank p and tells it whether p < L
-        const int c = bitonic_select(met, ncand, lane);
+        // lanes 0..L-1 hold the L smallest candidates and tell them so
+        const int c = bitonic_partition<L>(met, ncand, lane);
         keep = __builtin_amdgcn_ds_permute(c << 2, lane < L ? 1 : 0) != 0;
     } else {
         keep = threshold_keep<L>(met, ncand, lane);
