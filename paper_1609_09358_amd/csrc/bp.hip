@@ -74,9 +74,12 @@ __device__ __forceinline__ uint64_t lane_bits(const uint8_t* src, int lane) {
 // other half of its row of sixteen by the half-row and row mirrors (for a
 // reduction any lane of the other half serves); lane ^ 16, ^ 32 by the gfx950
 // row swaps.
+// lane permutation CTRL of v (a full permutation of each row: every lane is
+// written); the zero "old" value lets the compiler fold the move into the XOR
+// that takes it
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 // XOR of s over each group of TL consecutive lanes (TL a power of two <= 64);
@@ -175,13 +178,50 @@ __device__ __forceinline__ bool crc_check(const CodeDev& code, const uint8_t* ub
     return group_xor<G::TL>(s) == 0;
 }
 
-// LDS of one workgroup: transpose buffers and the packed-decision staging
+// LDS of one workgroup: transpose buffers, the packed-decision staging and
+// the wavefronts' partial CRC syndromes (two sets, taken by iteration parity)
 template <class G>
 struct BpShared {
     float tb[G::TAB.words];
     __attribute__((aligned(16))) uint8_t ubytes[G::FPW * G::N];
     __attribute__((aligned(16))) uint8_t xbytes[G::FPW * G::N];
+    uint32_t syn[2][G::NWAVES];
 };
+
+// CRC test of a frame of at least one wavefront whose thread t holds its own
+// packed decisions, nodes 8t .. 8t + 7 (nibble positions 2t and 2t + 1): each
+// thread XORs the syndromes of its two nibbles, each wavefront reduces its
+// lanes, and the frame's wavefronts combine their words through LDS.  syn is
+// one of two sets taken by iteration parity: a wavefront's next write goes to
+// the other set, and the one after it follows the next test's barrier, which
+// every wavefront reaches only after its reads.  Every thread of the frame gets
+// the answer; ends with a frame-wide barrier.
+template <class G>
+__device__ __forceinline__ bool crc_check_own(const CodeDev& code, uint32_t bits, int t, uint32_t* syn) {
+    static_assert(G::V == 8 && G::T >= 64, "packed decisions of whole wavefronts");
+    uint32_t s = 0;
+    if (code.c != 0) {
+        // byte offsets of the two table entries (bits < 256) from the
+        // table's uniform base: 32-bit lane offsets, no per-lane pointer
+        const uint8_t* tab = reinterpret_cast<const uint8_t*>(code.syn_nib);
+        const uint32_t row = (uint32_t)t << 7;
+        const uint32_t o0 = row | ((bits & 15u) << 2);
+        const uint32_t o1 = row | 64u | ((bits >> 2) & 0x3Cu);
+        s = group_xor<64>(*reinterpret_cast<const uint32_t*>(tab + o0) ^
+                          *reinterpret_cast<const uint32_t*>(tab + o1));
+    }
+    if constexpr (G::NWAVES == 1) {
+        frame_sync<G>();
+        return s == 0;
+    } else {
+        if ((t & 63) == 0) syn[t >> 6] = s;
+        frame_sync<G>();
+        uint32_t a = 0;
+#pragma unroll
+        for (int w = 0; w < G::NWAVES; ++w) a ^= syn[w];
+        return a == 0;
+    }
+}
 
 // Where one frame's data lives.  SAVE (training): every message a column
 // produces is also written to sv[iteration][direction][column][node],
@@ -258,6 +298,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
 
     int it = 0;
     bool gok = false, cok = false;
+    uint32_t ubits = 0;  // packed decisions of this thread's nodes (BITPACK)
     while (true) {
         const float* Wit = WEIGHTED ? W + (size_t)it * 2 * n * (WSTAGE ? 1 : N) : nullptr;
         float* Sit = SAVE ? io.saved + (size_t)it * 2 * n * N : nullptr;
@@ -287,13 +328,15 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                                 wi = w[v << G::wbase(k)];
                                 wj = w[v2 << G::wbase(k)];
                             }
-                            const float si = sign_to(wi, r1);
-                            const float sj = WSTAGE ? si : sign_to(wj, r1);
+                            // column 0: r1 is the prior, 0 or lmax > 0, whose
+                            // sign leaves the weight as it is
+                            const float si = (s == 0) ? wi : sign_to(wi, r1);
+                            const float sj = WSTAGE ? si : ((s == 0) ? wj : sign_to(wj, r1));
                             const float yi = si * clamp_mag(x, r1);
                             Rm[s + 1][v] = NOCLIP ? yi : clipf(yi, lmax);
                             Rm[s + 1][v2] = clipf(__fmaf_rn(sj, clamp_mag(l1, r1), r2), lmax);
                         } else {
-                            const float si = sign_to(1.0f, r1);
+                            const float si = (s == 0) ? 1.0f : sign_to(1.0f, r1);
                             Rm[s + 1][v] = si * clamp_mag(x, r1);  // |g| <= |r1| <= lmax
                             Rm[s + 1][v2] = clipf(__fmaf_rn(si, clamp_mag(l1, r1), r2), lmax);
                         }
@@ -414,14 +457,19 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
         });
         // ---------------- decisions in window 0 (register bits are the low bits)
         if constexpr (BITPACK) {
-            // nodes 8t .. 8t + 7: byte t of the bit array
-            uint32_t bits = 0;
+            // nodes 8t .. 8t + 7: byte t of the bit array.  LLR(u) = L + prior
+            // is never -0 (the prior is +0 or lmax > 0, and a sum of zeros of
+            // opposite signs rounds to +0), so its sign bit is the test
+            // LLR(u) < 0; each bit is shifted in from the sign (one funnel
+            // shift), frozen nodes are cleared after
+            ubits = 0;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const float lu = Lm[0][v] + prior[v];
-                bits |= (((fmask >> v) & 1u) == 0 && lu < 0.0f) ? (1u << v) : 0u;
-            }
-            ub[t] = (uint8_t)bits;
+            for (int v = V - 1; v >= 0; --v)
+                ubits = __builtin_amdgcn_alignbit(ubits, __float_as_uint(Lm[0][v] + prior[v]), 31);
+            ubits &= ~fmask;
+            // the CRC stop tests every thread's own bits and stores them once,
+            // after the loop
+            if (stop != 2) ub[t] = (uint8_t)ubits;
         } else {
             uint64_t pack = 0;
 #pragma unroll
@@ -452,8 +500,12 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
                 break;
             }
         } else if (stop == 2) {
-            frame_sync<G>();
-            cok = crc_check<G, BITPACK>(code, ub, lane);
+            if constexpr (BITPACK) {
+                cok = crc_check_own<G>(code, ubits, t, sh.syn[it & 1]);
+            } else {
+                frame_sync<G>();
+                cok = crc_check<G, BITPACK>(code, ub, lane);
+            }
             if (cok || last) break;
         } else if (last) {
             frame_sync<G>();
@@ -470,7 +522,7 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
         if (io.u_hat) {
             uint8_t* uo = io.u_hat + ib;
             if constexpr (BITPACK) {
-                const uint32_t ubits = ub[t];  // the last iteration's decisions
+                // ubits: the last iteration's decisions
                 uint64_t bytes = 0;
 #pragma unroll
                 for (int v = 0; v < V; ++v) bytes |= (uint64_t)((ubits >> v) & 1u) << (8 * v);
@@ -487,6 +539,13 @@ __device__ __forceinline__ bool bp_frame(const CodeDev& code, const FrameIO& io,
             // row 0 still holds the last iteration's L messages (the loop
             // leaves right after the decisions that read it)
             for (int v = 0; v < V; ++v) lo[v] = Lm[0][v] + prior[v];
+        }
+        if constexpr (BITPACK) {
+            if (stop == 2 && io.info && okv) {
+                // the CRC stop left the bits in registers (frame-uniform branch)
+                ub[t] = (uint8_t)ubits;
+                frame_sync<G>();
+            }
         }
         if (io.info && okv) {
             // the hybrid keeps BP's result: its information bits go out here
