@@ -97,6 +97,13 @@ __device__ __forceinline__ glb_ptr<T> as_glb(const void* p) {
 // through it becomes scalar or uniform-address work)
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 template <typename T>
+__device__ __forceinline__ glb_ptr<T> uniform_glb(glb_ptr<T> p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (glb_ptr<T>)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -357,6 +364,148 @@ struct Layout {
     int64_t u_stride;  // u_hat row stride of a ragged batch
 };
 
+// Levels top..5 of every path at a block start (top = the highest level whose
+// index bit changed).  Level 5 of a path is 32 items, taken as eight groups of
+// four; group g of path p is one chain, run by lane 8 (p mod 8) + g as its
+// chain p / 8.  A chain's items of level d are the items e + 32 k of its group
+// e, and each depends only on the same chain's items of level d + 1, so a
+// lane computes its chains from level top + 1 alone, in registers: the level
+// top items are the leaves, taken in bit-reversed order so that each pair of
+// consecutive results at one level combines at once into the level below
+// (a stack of one pending value per level); every item is stored on the way
+// for the later bits and blocks, and nothing stored here is read back here.
+// The chains of a lane run as one stream of leaves, the loads of the next P
+// leaves in flight (two where the stack is deep, N >= 2048, to stay within the
+// register budget).  H = top - 5.
+struct Leaf {
+    f32x4 a, b;   // items e and e + 2^top of level top + 1
+    uint32_t w;   // partial-sum bits of the four items (g at the top level)
+};
+
+// where a block start reads level top + 1 (one kind per block start, so the
+// leaf loop has no branch between loads of different kinds, whose joins would
+// make every load wait at once): 16-byte loads from global memory (the
+// workgroup's slice, or the channel row with stride 0), 16-byte loads from
+// LDS, or single loads from a channel row not 16-byte aligned
+enum : int { kSrcGlobal = 0, kSrcLds = 1, kSrcChan1 = 2 };
+
+template <int H, int SRC, int P = (H <= 4 ? 4 : 2)>
+__device__ __forceinline__ void block_levels(const int top, const int act, const int lane, const int N, const int gl,
+                                             const int SL, const int PW, const lds_ptr<float> slam,
+                                             const glb_ptr<float> glam, const glb_ptr<const float> gsrc,
+                                             const int gstride, const lds_ptr<uint32_t> psw, const bool psum,
+                                             const uint32_t srcpack, const uint32_t psspack) {
+    constexpr int BS = 32;
+    constexpr int M = 1 << H;            // leaves per chain
+    const int C = (act + 7) >> 3;        // chains per lane
+    const int S = C << H;                // leaves per lane
+    // the lane index made opaque here, so that the lane offsets below are
+    // computed at each block start instead of being hoisted out of the frame
+    // loop and held in registers throughout
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int e4 = (ln & 7) << 2;        // the group's first item
+    const int szt = 1 << top;
+    const int lofs = (2 << top) - BS;    // level top + 1 inside an LDS slot
+    auto leaf_k = [&](int m) -> int { return H == 0 ? 0 : (int)(__builtin_bitreverse32((uint32_t)m) >> (32 - H)); };
+    auto load = [&](int st) -> Leaf {
+        Leaf o;
+        const int c = st >> H;
+        const int it = e4 + 32 * leaf_k(st & (M - 1));
+        const int src = (int)((srcpack >> (8 * c)) & 0xFFu);
+        if constexpr (SRC == kSrcGlobal) {
+            // 32-bit byte offsets from the uniform base (the slice and a row
+            // are far below 4 GB): one offset register per load
+            const uint32_t off = (uint32_t)(src * gstride + it) * 4u;
+            o.a = *(glb_ptr<const f32x4>)((glb_ptr<const char>)gsrc + off);
+            o.b = *(glb_ptr<const f32x4>)((glb_ptr<const char>)gsrc + off + 4u * (uint32_t)szt);
+        } else if constexpr (SRC == kSrcLds) {
+            const lds_ptr<float> q = slam + src * SL + lofs + it;
+            o.a = *(lds_ptr<const f32x4>)q;
+            o.b = *(lds_ptr<const f32x4>)(q + szt);
+        } else {
+            const glb_ptr<const float> q = gsrc + it;
+            o.a = f32x4{q[0], q[1], q[2], q[3]};
+            o.b = f32x4{q[szt], q[szt + 1], q[szt + 2], q[szt + 3]};
+        }
+        // the partial sums (read also where they are not used: the slot
+        // pointers of the first block are valid)
+        const int pss = (int)((psspack >> (8 * c)) & 0xFFu);
+        o.w = psw[pss * PW + ps_off(top) + leaf_k(st & (M - 1))] >> e4;
+        return o;
+    };
+    auto put = [&](int d, int slot, int it, const f32x4& v) {
+        if (d < gl) *(lds_ptr<f32x4>)(slam + slot * SL + (1 << d) - BS + it) = v;
+        else *(glb_ptr<f32x4>)((glb_ptr<char>)glam + (uint32_t)(slot * N + (1 << d) + it) * 4u) = v;
+    };
+    // every load and the partial-sum read are issued unconditionally (a load
+    // past the stream's end repeats the last leaf's), so the waits for a
+    // leaf's data leave the later leaves' loads in flight; only the stores
+    // of paths past the list's end are skipped
+    Leaf ring[P];
+    f32x4 stk[H > 0 ? H : 1];
+    auto step = [&](const int st, Leaf& slotq) {
+        const Leaf x = slotq;
+        slotq = load(st + P < S ? st + P : S - 1);
+        const int m = st & (M - 1);
+        const int k = leaf_k(m);
+        const int slot = (ln >> 3) + 8 * (st >> H);
+        const bool live = slot < act;
+        f32x4 v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = psum ? (((x.w >> i) & 1u) ? x.b[i] - x.a[i] : x.b[i] + x.a[i]) : f_ms(x.a[i], x.b[i]);
+        if (live) put(top, slot, e4 + 32 * k, v);
+        bool go = true;
+        static_for<0, H>([&](auto LC) {
+            constexpr int l = decltype(LC)::value;
+            if (go) {
+                if ((m >> l) & 1) {
+                    f32x4 u;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) u[i] = f_ms(stk[l][i], v[i]);
+                    v = u;
+                    if (live) put(top - l - 1, slot, e4 + 32 * (k & ((M >> (l + 1)) - 1)), v);
+                } else {
+                    stk[l] = v;
+                    go = false;
+                }
+            }
+        });
+    };
+#pragma unroll
+    for (int q = 0; q < P; ++q) ring[q] = load(q < S ? q : S - 1);
+    if (S % P == 0) {
+        for (int s0 = 0; s0 < S; s0 += P) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) step(s0 + q, ring[q]);
+        }
+    } else {
+        // a stream shorter than P or not a multiple of it (a list of fewer
+        // than 25 paths at the lowest levels)
+        for (int s0 = 0; s0 < S; s0 += P) {
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                if (s0 + q < S) step(s0 + q, ring[q]);
+        }
+    }
+}
+
+template <int H>
+__device__ __forceinline__ void block_levels_at(const int src_kind, const int top, const int act, const int lane,
+                                                const int N, const int gl, const int SL, const int PW,
+                                                const lds_ptr<float> slam, const glb_ptr<float> glam,
+                                                const glb_ptr<const float> gsrc, const int gstride,
+                                                const lds_ptr<uint32_t> psw, const bool psum, const uint32_t srcpack,
+                                                const uint32_t psspack) {
+    if (src_kind == kSrcGlobal)
+        block_levels<H, kSrcGlobal>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
+    else if (src_kind == kSrcLds)
+        block_levels<H, kSrcLds>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
+    else
+        block_levels<H, kSrcChan1>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
+}
+
 template <int L, int BL, int RANK = kRankCount>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void scl_kernel(CodeDev code_in, const float* __restrict__ llr,
                                                  const int32_t* __restrict__ frame_ids,
@@ -440,102 +589,64 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
             const uint32_t dword = (uint32_t)__builtin_amdgcn_readlane((int)(wi < 64 ? dav0 : dav1), wi & 63);
             const uint32_t fw = (fword >> (i0 & 31)) & bmask;
             const uint32_t dw = (dword >> (i0 & 31)) & bmask;  // decision-aided
-            // the block's CRC syndromes, lane r holding position i0 + r
-            const uint32_t synv = synp[i0 + (lane & (BS - 1))];
+            // the block's CRC syndromes, lane r holding position i0 + r (loaded
+            // after the block start's fence, which would otherwise wait for it)
+            uint32_t synv = 0u;
+            bool syn_loaded = false;
+            // ---------------- block start: levels top..BL of every path
+            if constexpr (BL == 5) {
+                if (BL < n) {
+                    const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
+                    // slots read at level top + 1 and partial sums at level top,
+                    // of each chain's path: byte c for chain c of this lane
+                    const int myp = get_byte(ptrL, top + 1);
+                    const int mypp = get_byte(ptrP, top);
+                    uint32_t srcpack = 0u, psspack = 0u;
+#pragma unroll
+                    for (int c = 0; c < (L + 7) / 8; ++c) {
+                        const int pth = (lane >> 3) + 8 * c;
+                        srcpack |= (uint32_t)__shfl(myp, pth, 64) << (8 * c);
+                        psspack |= (uint32_t)__shfl(mypp, pth, 64) << (8 * c);
+                    }
+                    const bool psum = j != 0;
+                    // level top + 1: the channel row (same for every path), LDS,
+                    // or the workgroup's global slice
+                    const bool in_chan = top + 1 == n;
+                    const int kind = in_chan ? (chan16 ? kSrcGlobal : kSrcChan1) : (top + 1 < gl ? kSrcLds : kSrcGlobal);
+                    const glb_ptr<const float> gsrc =
+                        uniform_glb(in_chan ? chan : (glb_ptr<const float>)(glam + (2 << top)));
+                    const int gstride = in_chan ? 0 : N;
+                    // the levels above were written by other lanes at earlier
+                    // block starts
+                    wg_mem_order();
+                    synv = synp[i0 + (lane & (BS - 1))];
+                    syn_loaded = true;
+                    switch (top - BL) {
+                        case 0: block_levels_at<0>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 1: block_levels_at<1>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 2: block_levels_at<2>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 3: block_levels_at<3>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 4: block_levels_at<4>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 5: block_levels_at<5>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        default: block_levels_at<6>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                    }
+                    // level 5 (LDS) is read by the block's bits
+                    wave_mem_order();
+                    if (lane < act)
+                        for (int d = top; d >= BL; --d) set_byte(ptrL, d, lane);
+                }
+            }
+            if (!syn_loaded) synv = synp[i0 + (lane & (BS - 1))];
             // the block's register levels and partial sums are all rewritten
             // before they are read again (lanes that join the list during the
-            // block pull what they read), so they carry nothing into the block
-            // start and its passes may use their registers
+            // block pull what they read): they carry nothing from the last block,
+            // and the block start above had their registers
 #pragma unroll
             for (int e = 0; e < 32; ++e) lv[e] = 0.0f;
 #pragma unroll
             for (int d = 0; d < 5; ++d) ps[d] = 0u;
             ublk = 0u;
             anc = lane;
-            // ---------------- block start: levels top..BL, all lanes together
-            if (BL < n) {
-                const int top = (j == 0) ? n - 1 : __builtin_ctz((unsigned)i0);
-                for (int d = top; d >= BL; --d) {
-                    const int sz = 1 << d;
-                    const int myp = get_byte(ptrL, d + 1);
-                    const int mypp = get_byte(ptrP, d);
-                    // units of four consecutive items of one slot (a level has at
-                    // least 32 per slot), UP units per lane per pass with all loads
-                    // issued before any use (the loads of a level in the global
-                    // slice take a trip through the memory hierarchy, so a pass
-                    // keeps several in flight; the registers of the block's lower
-                    // levels are free here); every lane runs every pass, so the lane
-                    // shuffles read active lanes only (units past the end redo unit
-                    // 0 and store nothing)
-                    constexpr int UP = 4;
-                    const int units = act << (d - 2);
-                    const bool psum = d == top && j != 0;
-                    for (int u0 = 0; u0 < units; u0 += 64 * UP) {
-                        float a[UP][4], b[UP][4];
-                        int slot[UP], e[UP];
-                        bool live[UP];
-#pragma unroll
-                        for (int h = 0; h < UP; ++h) {
-                            const int uu = u0 + 64 * h + lane;
-                            live[h] = uu < units;
-                            const int it = (live[h] ? uu : 0) << 2;
-                            slot[h] = it >> d;
-                            e[h] = it & (sz - 1);
-                            if (d + 1 == n) {
-                                if (chan16) {
-                                    const f32x4 ta = *(glb_ptr<const f32x4>)(chan + e[h]);
-                                    const f32x4 tb = *(glb_ptr<const f32x4>)(chan + e[h] + sz);
-                                    a[h][0] = ta.x; a[h][1] = ta.y; a[h][2] = ta.z; a[h][3] = ta.w;
-                                    b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
-                                } else {
-#pragma unroll
-                                    for (int k = 0; k < 4; ++k) {
-                                        a[h][k] = chan[e[h] + k];
-                                        b[h][k] = chan[e[h] + sz + k];
-                                    }
-                                }
-                            } else {
-                                const int src = (d == top) ? __shfl(myp, slot[h], 64) : slot[h];
-                                f32x4 ta, tb;
-                                if (d + 1 < gl) {
-                                    const lds_ptr<float> p = slam + src * SL + ((2 << d) - BS) + e[h];
-                                    ta = *(lds_ptr<const f32x4>)p;
-                                    tb = *(lds_ptr<const f32x4>)(p + sz);
-                                } else {
-                                    const glb_ptr<float> p = glam + (size_t)src * N + (2 << d) + e[h];
-                                    ta = *(glb_ptr<const f32x4>)p;
-                                    tb = *(glb_ptr<const f32x4>)(p + sz);
-                                }
-                                a[h][0] = ta.x; a[h][1] = ta.y; a[h][2] = ta.z; a[h][3] = ta.w;
-                                b[h][0] = tb.x; b[h][1] = tb.y; b[h][2] = tb.z; b[h][3] = tb.w;
-                            }
-                        }
-                        uint32_t w[UP] = {};
-                        if (psum) {
-#pragma unroll
-                            for (int h = 0; h < UP; ++h) {
-                                const int pss = __shfl(mypp, slot[h], 64);
-                                w[h] = psw[pss * PW + ps_off(d) + (e[h] >> 5)] >> (e[h] & 31);
-                            }
-                        }
-#pragma unroll
-                        for (int h = 0; h < UP; ++h) {
-                            float v[4];
-#pragma unroll
-                            for (int k = 0; k < 4; ++k)
-                                v[k] = psum ? (((w[h] >> k) & 1u) ? b[h][k] - a[h][k] : b[h][k] + a[h][k])
-                                            : f_ms(a[h][k], b[h][k]);
-                            if (live[h]) {
-                                const f32x4 o = {v[0], v[1], v[2], v[3]};
-                                if (d < gl) *(lds_ptr<f32x4>)(slam + slot[h] * SL + sz - BS + e[h]) = o;
-                                else *(glb_ptr<f32x4>)(glam + (size_t)slot[h] * N + sz + e[h]) = o;
-                            }
-                        }
-                    }
-                    if (d < gl) wave_mem_order(); else wg_mem_order();
-                    if (lane < act) set_byte(ptrL, d, lane);
-                }
-            }
             // ---------------- the 2^BL bits of the block, unrolled
             static_for<0, BS>([&](auto RC) {
                 constexpr int r = decltype(RC)::value;
