@@ -8,9 +8,9 @@
 // values, level n is the channel) and its partial sums (level d holds 2^d
 // bits) are split in two:
 //   - levels below BL = min(n, 5) live in the registers of the owning lane;
-//   - levels BL and above live in LDS (the largest ones optionally in a global
-//     slice) and are shared lazily: each slot keeps, per level, the slot whose
-//     array it reads.  Bit i rewrites levels ctz(i)..BL of every path into the
+//   - level BL lives in LDS and the levels above it in the workgroup's global
+//     slice (partial sums of levels >= 5 in LDS); they are shared lazily:
+//     each slot keeps, per level, the slot whose array it reads.  Bit i rewrites levels ctz(i)..BL of every path into the
 //     path's own slot and reads level ctz(i)+1 through the pointer, which no
 //     path writes during bit i; partial sums are handled the same way.
 // Bits are processed in blocks of 2^BL.  Inside a block, ctz(i) and the number
@@ -39,8 +39,8 @@
 // A frame's decode is a long chain of dependent steps, so throughput comes
 // from many frames in flight: the kernel is held to 128 VGPRs (four waves per
 // SIMD) and the LDS state is sized to let sixteen one-wave workgroups share a
-// CU.  What does not fit moves to the workgroup's global slice: first the
-// trace (5 bytes per block and path), then the largest tree levels.
+// CU; the trace (5 bytes per block and path) moves to the workgroup's global
+// slice when it does not fit.
 #include <atomic>
 #include <type_traits>
 
@@ -353,7 +353,7 @@ __device__ __forceinline__ int select_survivors(lds_ptr<uint32_t> mets, float me
 }
 
 struct Layout {
-    int gl;      // LLR levels < gl in LDS, the others in the workgroup's global slice
+    int gl;      // LLR levels < gl in LDS (gl = min(n, 6)), the others in the workgroup's global slice
     int sl;      // LDS floats per slot: levels BL..gl-1, level d at offset 2^d - 2^BL, padded
     int pw;      // partial-sum words per slot (levels >= 5)
     int tg;      // 1: the trace lives in the global slice and is read back in chunks
@@ -373,99 +373,103 @@ struct Layout {
 // top items are the leaves, taken in bit-reversed order so that each pair of
 // consecutive results at one level combines at once into the level below
 // (a stack of one pending value per level); every item is stored on the way
-// for the later bits and blocks, and nothing stored here is read back here.
+// for the later bits and blocks (level 5 in LDS, the levels above in the
+// workgroup's global slice), and nothing stored here is read back here.
 // The chains of a lane run as one stream of leaves, the loads of the next P
 // leaves in flight (two where the stack is deep, N >= 2048, to stay within the
-// register budget).  H = top - 5.
+// register budget).  Every load is issued unconditionally (a load past the
+// stream's end repeats the last leaf's), so the waits for one leaf's data
+// leave the later leaves' loads outstanding.  With L >= 8 the chains of
+// paths past the list's end (slots below 8 * chains <= L) store too: those
+// slots' levels top..5 are rewritten before any path reads them.  H = top - 5.
 struct Leaf {
     f32x4 a, b;   // items e and e + 2^top of level top + 1
     uint32_t w;   // partial-sum bits of the four items (g at the top level)
 };
 
-// where a block start reads level top + 1 (one kind per block start, so the
-// leaf loop has no branch between loads of different kinds, whose joins would
-// make every load wait at once): 16-byte loads from global memory (the
-// workgroup's slice, or the channel row with stride 0), 16-byte loads from
-// LDS, or single loads from a channel row not 16-byte aligned
-enum : int { kSrcGlobal = 0, kSrcLds = 1, kSrcChan1 = 2 };
-
-template <int H, int SRC, int P = (H <= 4 ? 4 : 2)>
-__device__ __forceinline__ void block_levels(const int top, const int act, const int lane, const int N, const int gl,
-                                             const int SL, const int PW, const lds_ptr<float> slam,
-                                             const glb_ptr<float> glam, const glb_ptr<const float> gsrc,
-                                             const int gstride, const lds_ptr<uint32_t> psw, const bool psum,
-                                             const uint32_t srcpack, const uint32_t psspack) {
-    constexpr int BS = 32;
-    constexpr int M = 1 << H;            // leaves per chain
-    const int C = (act + 7) >> 3;        // chains per lane
-    const int S = C << H;                // leaves per lane
+template <int L, int H, bool CHAN1>
+__device__ __forceinline__ void block_levels(const int act, const int lane, const int N, const int SL, const int PW,
+                                             const lds_ptr<float> slam, const glb_ptr<float> glam,
+                                             const glb_ptr<const float> gsrc, const int gstride,
+                                             const lds_ptr<uint32_t> psw, const bool psum, const uint32_t srcpack,
+                                             const uint32_t psspack) {
+    constexpr int TOP = H + 5;
+    constexpr int M = 1 << H;             // leaves per chain
+    constexpr int P = H <= 4 ? 4 : 2;     // leaves in flight
+    constexpr int LP = P == 4 ? 2 : 1;    // log2 P
+    constexpr int SZT = 1 << TOP;
+    const int C = (act + 7) >> 3;         // chains per lane
+    const int S = C << H;                 // leaves per lane
     // the lane index made opaque here, so that the lane offsets below are
     // computed at each block start instead of being hoisted out of the frame
     // loop and held in registers throughout
     int ln = lane;
     asm volatile("" : "+v"(ln));
-    const int e4 = (ln & 7) << 2;        // the group's first item
-    const int szt = 1 << top;
-    const int lofs = (2 << top) - BS;    // level top + 1 inside an LDS slot
-    auto leaf_k = [&](int m) -> int { return H == 0 ? 0 : (int)(__builtin_bitreverse32((uint32_t)m) >> (32 - H)); };
+    const int e4 = (ln & 7) << 2;         // the group's first item
+    auto leaf_k = [](int m) -> int { return H == 0 ? 0 : (int)(__builtin_bitreverse32((uint32_t)m) >> (32 - H)); };
     auto load = [&](int st) -> Leaf {
         Leaf o;
         const int c = st >> H;
-        const int it = e4 + 32 * leaf_k(st & (M - 1));
-        const int src = (int)((srcpack >> (8 * c)) & 0xFFu);
-        if constexpr (SRC == kSrcGlobal) {
-            // 32-bit byte offsets from the uniform base (the slice and a row
-            // are far below 4 GB): one offset register per load
+        const int k = leaf_k(st & (M - 1));
+        const int it = e4 + 32 * k;
+        if constexpr (!CHAN1) {
+            // level top + 1 of the chain's source slot (stride 0: the channel
+            // row), 32-bit byte offsets from the uniform base
+            const int src = (int)((srcpack >> (8 * c)) & 0xFFu);
             const uint32_t off = (uint32_t)(src * gstride + it) * 4u;
             o.a = *(glb_ptr<const f32x4>)((glb_ptr<const char>)gsrc + off);
-            o.b = *(glb_ptr<const f32x4>)((glb_ptr<const char>)gsrc + off + 4u * (uint32_t)szt);
-        } else if constexpr (SRC == kSrcLds) {
-            const lds_ptr<float> q = slam + src * SL + lofs + it;
-            o.a = *(lds_ptr<const f32x4>)q;
-            o.b = *(lds_ptr<const f32x4>)(q + szt);
+            o.b = *(glb_ptr<const f32x4>)((glb_ptr<const char>)gsrc + off + 4u * SZT);
         } else {
             const glb_ptr<const float> q = gsrc + it;
             o.a = f32x4{q[0], q[1], q[2], q[3]};
-            o.b = f32x4{q[szt], q[szt + 1], q[szt + 2], q[szt + 3]};
+            o.b = f32x4{q[SZT], q[SZT + 1], q[SZT + 2], q[SZT + 3]};
         }
         // the partial sums (read also where they are not used: the slot
         // pointers of the first block are valid)
         const int pss = (int)((psspack >> (8 * c)) & 0xFFu);
-        o.w = psw[pss * PW + ps_off(top) + leaf_k(st & (M - 1))] >> e4;
+        o.w = psw[pss * PW + ps_off(TOP) + k] >> e4;
         return o;
     };
-    auto put = [&](int d, int slot, int it, const f32x4& v) {
-        if (d < gl) *(lds_ptr<f32x4>)(slam + slot * SL + (1 << d) - BS + it) = v;
-        else *(glb_ptr<f32x4>)((glb_ptr<char>)glam + (uint32_t)(slot * N + (1 << d) + it) * 4u) = v;
-    };
-    // every load and the partial-sum read are issued unconditionally (a load
-    // past the stream's end repeats the last leaf's), so the waits for a
-    // leaf's data leave the later leaves' loads in flight; only the stores
-    // of paths past the list's end are skipped
     Leaf ring[P];
     f32x4 stk[H > 0 ? H : 1];
-    auto step = [&](const int st, Leaf& slotq) {
+    // leaf s0 + q, s0 a multiple of P: the chain and the low bits of the leaf's
+    // index in it are known at compile time where the chain is at least P long
+    auto step = [&](const int s0, auto QC, Leaf& slotq) {
+        constexpr int q = decltype(QC)::value;
         const Leaf x = slotq;
-        slotq = load(st + P < S ? st + P : S - 1);
-        const int m = st & (M - 1);
+        slotq = load(s0 + q + P < S ? s0 + q + P : S - 1);
+        const int m = M >= P ? ((s0 & (M - 1)) | q) : (q & (M - 1));
+        const int c = M >= P ? (s0 >> H) : ((s0 >> H) + (q >> H));
         const int k = leaf_k(m);
-        const int slot = (ln >> 3) + 8 * (st >> H);
-        const bool live = slot < act;
+        const int slot = (ln >> 3) + 8 * c;
+        const bool live = L >= 8 || slot < act;
+        auto put = [&](auto DC, int kk, const f32x4& v) {
+            constexpr int d = decltype(DC)::value;
+            if (!live) return;
+            if constexpr (d == 5) *(lds_ptr<f32x4>)(slam + slot * SL + e4 + 32 * kk) = v;
+            else *(glb_ptr<f32x4>)((glb_ptr<char>)glam + (uint32_t)(slot * N + (1 << d) + e4 + 32 * kk) * 4u) = v;
+        };
         f32x4 v;
+        if (psum) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            v[i] = psum ? (((x.w >> i) & 1u) ? x.b[i] - x.a[i] : x.b[i] + x.a[i]) : f_ms(x.a[i], x.b[i]);
-        if (live) put(top, slot, e4 + 32 * k, v);
+            for (int i = 0; i < 4; ++i) v[i] = ((x.w >> i) & 1u) ? x.b[i] - x.a[i] : x.b[i] + x.a[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = f_ms(x.a[i], x.b[i]);
+        }
+        put(std::integral_constant<int, TOP>{}, k, v);
         bool go = true;
         static_for<0, H>([&](auto LC) {
             constexpr int l = decltype(LC)::value;
+            // bit l of the leaf's index: compile-time below log2 P
+            const bool one = (M >= P && l < LP) ? ((q >> l) & 1) != 0 : ((m >> l) & 1) != 0;
             if (go) {
-                if ((m >> l) & 1) {
+                if (one) {
                     f32x4 u;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) u[i] = f_ms(stk[l][i], v[i]);
                     v = u;
-                    if (live) put(top - l - 1, slot, e4 + 32 * (k & ((M >> (l + 1)) - 1)), v);
+                    put(std::integral_constant<int, TOP - l - 1>{}, k & ((M >> (l + 1)) - 1), v);
                 } else {
                     stk[l] = v;
                     go = false;
@@ -476,34 +480,15 @@ __device__ __forceinline__ void block_levels(const int top, const int act, const
 #pragma unroll
     for (int q = 0; q < P; ++q) ring[q] = load(q < S ? q : S - 1);
     if (S % P == 0) {
-        for (int s0 = 0; s0 < S; s0 += P) {
-#pragma unroll
-            for (int q = 0; q < P; ++q) step(s0 + q, ring[q]);
-        }
+        for (int s0 = 0; s0 < S; s0 += P)
+            static_for<0, P>([&](auto QC) { step(s0, QC, ring[decltype(QC)::value]); });
     } else {
-        // a stream shorter than P or not a multiple of it (a list of fewer
-        // than 25 paths at the lowest levels)
-        for (int s0 = 0; s0 < S; s0 += P) {
-#pragma unroll
-            for (int q = 0; q < P; ++q)
-                if (s0 + q < S) step(s0 + q, ring[q]);
-        }
+        // a stream not a multiple of P (fewer than 25 paths, lowest levels)
+        for (int s0 = 0; s0 < S; s0 += P)
+            static_for<0, P>([&](auto QC) {
+                if (s0 + decltype(QC)::value < S) step(s0, QC, ring[decltype(QC)::value]);
+            });
     }
-}
-
-template <int H>
-__device__ __forceinline__ void block_levels_at(const int src_kind, const int top, const int act, const int lane,
-                                                const int N, const int gl, const int SL, const int PW,
-                                                const lds_ptr<float> slam, const glb_ptr<float> glam,
-                                                const glb_ptr<const float> gsrc, const int gstride,
-                                                const lds_ptr<uint32_t> psw, const bool psum, const uint32_t srcpack,
-                                                const uint32_t psspack) {
-    if (src_kind == kSrcGlobal)
-        block_levels<H, kSrcGlobal>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
-    else if (src_kind == kSrcLds)
-        block_levels<H, kSrcLds>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
-    else
-        block_levels<H, kSrcChan1>(top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack);
 }
 
 template <int L, int BL, int RANK = kRankCount>
@@ -609,10 +594,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                         psspack |= (uint32_t)__shfl(mypp, pth, 64) << (8 * c);
                     }
                     const bool psum = j != 0;
-                    // level top + 1: the channel row (same for every path), LDS,
-                    // or the workgroup's global slice
+                    // level top + 1: the channel row (same for every path) or
+                    // the workgroup's global slice
                     const bool in_chan = top + 1 == n;
-                    const int kind = in_chan ? (chan16 ? kSrcGlobal : kSrcChan1) : (top + 1 < gl ? kSrcLds : kSrcGlobal);
+                    const bool chan1 = in_chan && !chan16;
                     const glb_ptr<const float> gsrc =
                         uniform_glb(in_chan ? chan : (glb_ptr<const float>)(glam + (2 << top)));
                     const int gstride = in_chan ? 0 : N;
@@ -621,15 +606,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     wg_mem_order();
                     synv = synp[i0 + (lane & (BS - 1))];
                     syn_loaded = true;
+#define POLAR_BLOCK_LEVELS(HH)                                                                                   \
+    (chan1 ? block_levels<L, HH, true>(act, lane, N, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack) \
+           : block_levels<L, HH, false>(act, lane, N, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack))
                     switch (top - BL) {
-                        case 0: block_levels_at<0>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        case 1: block_levels_at<1>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        case 2: block_levels_at<2>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        case 3: block_levels_at<3>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        case 4: block_levels_at<4>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        case 5: block_levels_at<5>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
-                        default: block_levels_at<6>(kind, top, act, lane, N, gl, SL, PW, slam, glam, gsrc, gstride, psw, psum, srcpack, psspack); break;
+                        case 0: POLAR_BLOCK_LEVELS(0); break;
+                        case 1: POLAR_BLOCK_LEVELS(1); break;
+                        case 2: POLAR_BLOCK_LEVELS(2); break;
+                        case 3: POLAR_BLOCK_LEVELS(3); break;
+                        case 4: POLAR_BLOCK_LEVELS(4); break;
+                        case 5: POLAR_BLOCK_LEVELS(5); break;
+                        default: POLAR_BLOCK_LEVELS(6); break;
                     }
+#undef POLAR_BLOCK_LEVELS
                     // level 5 (LDS) is read by the block's bits
                     wave_mem_order();
                     if (lane < act)
@@ -928,11 +917,12 @@ polar_status scl_plan_dims(int n, int L, int64_t max_frames, SclPlan* plan) {
     const int N = 1 << n;
     scl::KernelFn fn = scl::pick(L, n, rank_kind(L));
     if (!fn) return set_error(POLAR_ERR_INVALID_ARG, "scl: L must be a power of two in [1, 32]");
-    const int gl_min = n < 6 ? n : 6;
-    // everything in LDS if it fits; otherwise the trace goes to the global
-    // slice first (written once per bit, read once), then the largest levels
+    // tree levels: level 5 in LDS (read by every bit of a block), the levels
+    // above in the workgroup's global slice (each written and read once per
+    // block start that reaches it, as a stream); the trace in LDS if it fits
+    // the budget, else in the global slice
+    const int gl = n < 6 ? n : 6;
     bool tg = false;
-    int gl = n;
     scl::LdsPlan lp = scl::lds_plan(L, N, n, gl, tg);
     size_t budget = (size_t)g_scl_lds_budget.load(std::memory_order_relaxed);
     if (budget == 0) {
@@ -943,7 +933,6 @@ polar_status scl_plan_dims(int n, int L, int64_t max_frames, SclPlan* plan) {
     }
     if (lp.bytes > budget) {
         tg = true;
-        while (gl > gl_min && scl::lds_plan(L, N, n, gl, tg).bytes > budget) --gl;
         lp = scl::lds_plan(L, N, n, gl, tg);
     }
     if (lp.bytes > 160 * 1024) return set_error(POLAR_ERR_UNSUPPORTED, "scl: list too large for LDS");
