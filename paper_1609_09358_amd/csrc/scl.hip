@@ -58,6 +58,14 @@ __device__ __forceinline__ float f_ms(float a, float b) {
     return __uint_as_float(__float_as_uint(m) ^ (__float_as_uint(a) & 0x80000000u));
 }
 
+// g(a, b) = b + (1 - 2u) a with the partial-sum bit u at bit position q of
+// word w (q known at compile time where it is called): the bit moved onto
+// a's sign, b - a being b + (-a), rounded alike
+__device__ __forceinline__ float g_bit(float a, float b, uint32_t w, int q) {
+    const uint32_t sb = (w << (31 - q)) & 0x80000000u;
+    return b + __uint_as_float(__float_as_uint(a) ^ sb);
+}
+
 __device__ __forceinline__ void wave_mem_order() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -452,7 +460,7 @@ __device__ __forceinline__ void block_levels(const int act, const int lane, cons
         f32x4 v;
         if (psum) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = ((x.w >> i) & 1u) ? x.b[i] - x.a[i] : x.b[i] + x.a[i];
+            for (int i = 0; i < 4; ++i) v[i] = g_bit(x.a[i], x.b[i], x.w, i);
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[i] = f_ms(x.a[i], x.b[i]);
@@ -678,7 +686,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                             const float a = (d == dhi) ? src[e] : lv[(2 << d) + e];
                             const float b = (d == dhi) ? src[e + (1 << d)] : lv[(2 << d) + e + (1 << d)];
                             if (r != 0 && d == top)
-                                lv[(1 << d) + e] = ((ps[d] >> e) & 1u) ? b - a : b + a;
+                                lv[(1 << d) + e] = g_bit(a, b, ps[d], e);
                             else
                                 lv[(1 << d) + e] = f_ms(a, b);
                         }
