@@ -328,12 +328,13 @@ int64_t polar_get_scl_lds_budget(void);
 
 /* How the list decoder finds the L survivors among the 2L candidates of a
  * branching bit (Sec. II-A describes the first two): 1 the pruned pseudo sort
- * -- each candidate counts the candidates before it; 2 a bitonic sort of the
- * candidates across the wavefront (list sizes 8 and 32, N >= 32); 3 threshold
+ * -- each candidate counts the candidates before it; 2 the bitonic sorting
+ * network across the wavefront, run until the L smallest candidates are
+ * separated (list sizes 8 and 32, N >= 32); 3 threshold
  * selection -- the L-th smallest metric found bit by bit with wavefront
  * ballots (list sizes 8, 16 and 32, N >= 32); other lists use the pseudo
- * sort.  0 (default) automatic: the bitonic sort for L = 32, where it
- * measured fastest on MI355X, the pseudo sort otherwise.  All decide
+ * sort.  0 (default) automatic: the bitonic network for L = 8 and 32, where
+ * it measured fastest on MI355X, the pseudo sort otherwise.  All decide
  * survival by the strict order (metric, parent position, bit) and keep the
  * survivors in the order the candidates are listed (parent position, then
  * bit), so results are identical.  Process-wide; host only; mode outside 0..3

@@ -256,7 +256,8 @@ def polar_get_scl_lds_budget() -> int:
 
 
 def polar_set_scl_ranking(mode: int):
-    """List decoder survivor selection: 0 automatic, 1 pruned pseudo sort, 2 bitonic sort."""
+    """List decoder survivor selection: 0 automatic, 1 pruned pseudo sort, 2 bitonic network,
+    3 threshold selection."""
     _check(lib().polar_set_scl_ranking(int(mode)))
 
 

@@ -898,9 +898,9 @@ LdsPlan lds_plan(int L, int N, int n, int gl, bool tg) {
 
 }  // namespace scl
 
-// candidate ranking: 0 automatic (the bitonic sort for L = 32, where it
-// measured fastest on MI355X; the counting rank below), 1 pruned pseudo sort
-// (counting), 2 bitonic sort, 3 threshold selection
+// candidate ranking: 0 automatic (the bitonic network for L = 8 and 32, where
+// it measured fastest on MI355X; the counting rank otherwise), 1 pruned pseudo
+// sort (counting), 2 bitonic network, 3 threshold selection
 static std::atomic<int> g_scl_rank_mode{0};
 
 static int rank_kind(int L) {
@@ -908,7 +908,7 @@ static int rank_kind(int L) {
         case 1: return scl::kRankCount;
         case 2: return scl::kRankBitonic;
         case 3: return scl::kRankThreshold;
-        default: return L == 32 ? scl::kRankBitonic : scl::kRankCount;
+        default: return (L == 32 || L == 8) ? scl::kRankBitonic : scl::kRankCount;
     }
 }
 
