@@ -73,7 +73,7 @@ ITER_SCHEDULE = ((1e-3, 1500),)
 # written), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a device copy of
 # known size; valid only for the kernel sources they were measured on (hash of
 # the files below) and that stop rule
-BP_TRAFFIC = {"bytes": 354731728, "frames": 65536, "stop": 2, "src_sha256_16": "7fbfbbecc642d8ec"}
+BP_TRAFFIC = {"bytes": 354132792, "frames": 65536, "stop": 2, "src_sha256_16": "7fbfbbecc642d8ec"}
 BP_SOURCES = ("paper_1609_09358_amd/csrc/bp.hip", "paper_1609_09358_amd/csrc/bp_common.hpp",
               "paper_1609_09358_amd/csrc/bp_geom.hpp")
 

@@ -293,6 +293,24 @@ def test_scl_frame_subset_scatters_rows():
     assert np.all(uh[others] == 0)
 
 
+@pytest.mark.parametrize("N,K,c,L", [(256, 120, 8, 8), (1024, 512, 24, 32)])
+def test_scl_unaligned_channel_rows(N, K, c, L):
+    """Channel rows that do not start on a 16-byte boundary (the LLR buffer
+    one float past an allocation's start): the list decoder reads them with
+    single loads and decodes as the oracle does."""
+    B = 7
+    code, info, u, x, llr = frames(N, K, c, 2.0, 1.0, B, seed=5 * N + L)
+    buf = torch.zeros(B * N + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(llr).reshape(-1)
+    view = buf[1:].view(B, N)
+    assert view.data_ptr() % 16 != 0
+    ref = O.scl_batch(llr, code.frozen, L, c, POLY[c], prec="f32")
+    out = PB.scl_decode_batch(code, view, L)
+    assert np.array_equal(host(out["crc_ok"]), ref["crc_ok"])
+    assert np.array_equal(host(out["pm"]), ref["pm"].astype(np.float32))
+    assert np.array_equal(host(out["u_hat"]), ref["u_hat"])
+
+
 # ------------------------------------------------------------------ hybrid
 
 @pytest.mark.parametrize("stop", [1, 2])
