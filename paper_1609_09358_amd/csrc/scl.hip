@@ -649,8 +649,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                 constexpr int r = decltype(RC)::value;
                 // lowest level whose index bit changed at this bit (BL: block start)
                 constexpr int top = (r == 0) ? BL : ctz_c(r);
-                // levels still read by later bits of this block after bit r
-                constexpr int live_from = (r + 1 < BS) ? (2 << ctz_c(r + 1)) : 32;
+                // register level d (1 <= d < BL) is read next by the bit
+                // r' = r - (r mod 2^d) + 2^(d-1) and rewritten by bit
+                // r - (r mod 2^d) + 2^d: after bit r it is still to be read
+                // exactly when bit d - 1 of r is clear
+                constexpr unsigned live_levels = (r + 1 < BS) ? (~(unsigned)r & ((1u << (BL - 1)) - 1u)) : 0u;
                 // trailing ones of the bit index (>= BL at the block's last bit)
                 constexpr int tb = (r + 1 < BS) ? ctz_c(~r) : BL;
 
@@ -727,8 +730,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     ptrP.hi = shfl64(ptrP.hi, par);
 #pragma unroll
                     for (int d = 0; d < BL; ++d) ps[d] = __shfl(ps[d], par, 64);
+                    static_for<1, BL>([&](auto DC) {
+                        constexpr int d = decltype(DC)::value;
+                        if constexpr ((live_levels >> (d - 1)) & 1u) {
 #pragma unroll
-                    for (int e = live_from; e < BS; ++e) lv[e] = __shfl(lv[e], par, 64);
+                            for (int e = 1 << d; e < (2 << d); ++e) lv[e] = __shfl(lv[e], par, 64);
+                        }
+                    });
                     anc = __shfl(anc, par, 64);
                     ublk = __shfl(ublk, par, 64) | (cb << r);
                     if (lane < nact) bit = cb;
