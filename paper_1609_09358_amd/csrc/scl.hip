@@ -119,22 +119,22 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
     return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
-// 16 one-byte entries (slot read at each level) held in two 64-bit registers
+// the slot read at each shared level, one byte per level: only levels 5..12
+// are shared through slots (levels below 5 live in registers, N <= 4096), so
+// eight bytes, one 64-bit register pair, hold them all (a branch pulls one
+// pair per vector from the parent)
 struct PtrVec {
-    uint64_t lo, hi;
+    uint64_t w;
 };
 
 __device__ __forceinline__ int get_byte(const PtrVec& v, int idx) {
-    const uint64_t w = idx < 8 ? v.lo : v.hi;
-    return (int)((w >> (8 * (idx & 7))) & 0xFFull);
+    const int sh = idx > 5 ? 8 * (idx - 5) : 0;  // levels below 5 are never read here
+    return (int)((v.w >> sh) & 0xFFull);
 }
 
 __device__ __forceinline__ void set_byte(PtrVec& v, int idx, int val) {
-    const int sh = 8 * (idx & 7);
-    const uint64_t m = ~(0xFFull << sh);
-    const uint64_t add = (uint64_t)val << sh;
-    if (idx < 8) v.lo = (v.lo & m) | add;
-    else v.hi = (v.hi & m) | add;
+    const int sh = idx > 5 ? 8 * (idx - 5) : 0;
+    v.w = (v.w & ~(0xFFull << sh)) | ((uint64_t)val << sh);
 }
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
@@ -563,8 +563,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
         int act = 1;
         float PM = 0.0f;
         uint32_t SYN = 0u;
-        PtrVec ptrL{0ull, 0ull};  // slot read at each LLR level >= BL
-        PtrVec ptrP{0ull, 0ull};  // slot read at each partial-sum level >= 5
+        PtrVec ptrL{0ull};  // slot read at each LLR level >= BL
+        PtrVec ptrP{0ull};  // slot read at each partial-sum level >= 5
         float lv[32];             // levels 0..BL-1, heap order: level d at [2^d, 2^(d+1))
         uint32_t ps[5];           // partial-sum levels 0..BL-1: bit e of word d
 #pragma unroll
@@ -724,10 +724,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     // (lanes past the new list size pull lane 0's state, which no one reads)
                     PM = __shfl(met, c, 64);
                     SYN = __shfl(SYN, par, 64) ^ (cb ? syn_i : 0u);
-                    ptrL.lo = shfl64(ptrL.lo, par);
-                    ptrL.hi = shfl64(ptrL.hi, par);
-                    ptrP.lo = shfl64(ptrP.lo, par);
-                    ptrP.hi = shfl64(ptrP.hi, par);
+                    ptrL.w = shfl64(ptrL.w, par);
+                    ptrP.w = shfl64(ptrP.w, par);
 #pragma unroll
                     for (int d = 0; d < BL; ++d) ps[d] = __shfl(ps[d], par, 64);
                     static_for<1, BL>([&](auto DC) {
