@@ -726,8 +726,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void sc
                     SYN = __shfl(SYN, par, 64) ^ (cb ? syn_i : 0u);
                     ptrL.w = shfl64(ptrL.w, par);
                     ptrP.w = shfl64(ptrP.w, par);
-#pragma unroll
-                    for (int d = 0; d < BL; ++d) ps[d] = __shfl(ps[d], par, 64);
+                    // partial-sum level d is written at the bits r with r mod
+                    // 2^(d+1) = 2^d - 1 and read at those with r mod 2^(d+1) in
+                    // [2^d, 2^(d+1) - 1] (g at level d, then the fold at the
+                    // end of the 2^(d+1) block): after this point it is still to
+                    // be read exactly when bit d of r is set
+                    static_for<0, BL>([&](auto DC) {
+                        constexpr int d = decltype(DC)::value;
+                        if constexpr ((r >> d) & 1) ps[d] = __shfl(ps[d], par, 64);
+                    });
                     static_for<1, BL>([&](auto DC) {
                         constexpr int d = decltype(DC)::value;
                         if constexpr ((live_levels >> (d - 1)) & 1u) {
