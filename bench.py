@@ -146,7 +146,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); frames are independent, so a multi-GPU "
-              "run would shard the batch and is not part of this build", file=sys.stderr)
+              "run would shard the batch; it is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -837,7 +837,7 @@ def cpu_baseline(info, z, sigma2, frozen, N, K, C, L, T, W64, target_s, da=None)
     import oracle as O
 
     # every CPU this process may use, within the environment's thread budget
-    # (the CPU share of the GPU machine when it sets OMP_NUM_THREADS)
+    # (the CPU share the host grants when it sets OMP_NUM_THREADS)
     cpu = host_cpu()
     threads = cpu["usable"] if cpu["omp_num_threads"] is None else min(cpu["usable"], cpu["omp_num_threads"])
     threads = max(1, threads)

@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
     POLAR_OK = 0,
     POLAR_ERR_INVALID_ARG = 1, /* a pointer, size or parameter is out of range */
-    POLAR_ERR_UNSUPPORTED = 2, /* valid request this build does not implement   */
+    POLAR_ERR_UNSUPPORTED = 2, /* valid request the library does not implement  */
     POLAR_ERR_NO_MEMORY = 3,   /* host or device allocation failed (construction only) */
     POLAR_ERR_DEVICE = 4,      /* a HIP runtime call failed                       */
     POLAR_ERR_WORKSPACE = 5    /* workspace pointer missing or too small          */

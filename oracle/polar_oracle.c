@@ -15,7 +15,7 @@
  *                computes in 32-bit floating point).  Where a floating-point
  *                value decides an integer (a hard decision, the early-stop
  *                test, the iteration count, which list path survives) the GPU
- *                result is compared with this build, bit for bit.
+ *                result is compared with the REAL=float oracle, bit for bit.
  *
  * Everything is written for clarity, not speed: plain loops, one frame at a
  * time, no blocking, fusion or reordering beyond what each definition states.

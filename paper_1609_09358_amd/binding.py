@@ -44,8 +44,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"libpolarhip.so not found at {LIB_PATH}: run __graft_entry__.build() "
-                               "or python paper_1609_09358_amd/build.py")
+            raise RuntimeError(f"libpolarhip.so not found at {LIB_PATH}: build it with "
+                               "python paper_1609_09358_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
         L.polar_last_error.restype = C.c_char_p
