@@ -52,8 +52,14 @@ sys.path.insert(0, ROOT)
 
 # MI355X published figures
 HBM_PEAK_GBS = 8000.0
-CU, LANES, CLOCK_GHZ = 256, 64, 2.4
-VALU_PEAK_GOPS = CU * LANES * CLOCK_GHZ  # one 32-bit VALU operation per lane per clock
+# fp32 vector: 157.3 TFLOP/s counting a fused multiply-add as two operations,
+# i.e. 128 single-precision lane operations per CU per clock at 2.4 GHz, the
+# peak for the BP kernel's operations (add, multiply, fused multiply-add,
+# med3, bit operation) counted one each.  A stream of one operation kind
+# issues at half that (a probe of independent add, fma or med3 chains: 38 T/s);
+# the BP kernel's mixed stream measured above it (47 T VALU lane-instructions/s)
+CU, FP32_LANES_PER_CU_CLOCK, CLOCK_GHZ = 256, 128, 2.4
+VALU_PEAK_GOPS = CU * FP32_LANES_PER_CU_CLOCK * CLOCK_GHZ
 
 POLY24 = 0x864CFB
 # early stop of the learned BP: the CRC of the decided information bits (Sec.
@@ -432,9 +438,9 @@ def main():
 def kernel_times(code, llr, W, T, L, reps):
     """Average durations (HIP events on the stream the kernels are launched
     on) of the learned BP kernel alone on the batch and of the list decoder
-    alone on the frames that BP fails, each over `reps` launches after one
-    untimed launch; with the iteration sum of one BP launch (every launch
-    decodes the same frames)."""
+    alone on the frames that BP fails, each over `reps` launches after
+    untimed ones for 60 ms (the clock's steady state); with the iteration sum
+    of one BP launch (every launch decodes the same frames)."""
     import torch
 
     from paper_1609_09358_amd import binding as PB
@@ -442,9 +448,16 @@ def kernel_times(code, llr, W, T, L, reps):
     B, N = llr.shape
     stream = torch.cuda.current_stream()
 
-    def timed(fn):
+    def timed(fn, warm_ms=60.0):
+        # the clock needs a few tens of milliseconds of load to reach its
+        # steady state after the host-side work before: untimed launches
+        # until warm_ms have passed
+        t_w = time.perf_counter()
         fn()
         torch.cuda.synchronize()
+        while (time.perf_counter() - t_w) * 1e3 < warm_ms:
+            fn()
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -468,7 +481,7 @@ def kernel_times(code, llr, W, T, L, reps):
     scl_ms = timed(lambda: PB.scl_decode_batch(code, llr, L, frame_ids=fail_ids, out=scl_out,
                                                workspace=scl_ws)) if nfail else 0.0
     return {"bp_ms": bp_ms, "scl_ms": scl_ms, "scl_frames": nfail, "iter_sum": int(bp_out["iters"].sum().item()),
-            "launches_each": reps + 1, "bp_out": bp_out}
+            "timed_launches": reps, "bp_out": bp_out}
 
 
 def scl_ranking_ab(code, llr, bp_out, W, T, reps=3):
