@@ -55,9 +55,9 @@ HBM_PEAK_GBS = 8000.0
 # fp32 vector: 157.3 TFLOP/s counting a fused multiply-add as two operations,
 # i.e. 128 single-precision lane operations per CU per clock at 2.4 GHz, the
 # peak for the BP kernel's operations (add, multiply, fused multiply-add,
-# med3, bit operation) counted one each.  A stream of one operation kind
-# issues at half that (a probe of independent add, fma or med3 chains: 38 T/s);
-# the BP kernel's mixed stream measured above it (47 T VALU lane-instructions/s)
+# med3, bit operation) counted one each.  A probe of independent add, fma or
+# med3 chains, of one kind or mixed, issues at half that (38 T/s); the BP
+# kernel measured above it (47.6 T VALU lane-instructions/s)
 CU, FP32_LANES_PER_CU_CLOCK, CLOCK_GHZ = 256, 128, 2.4
 VALU_PEAK_GOPS = CU * FP32_LANES_PER_CU_CLOCK * CLOCK_GHZ
 
