@@ -279,8 +279,8 @@ def main():
         return time.perf_counter() - t0
 
     # ---- timed region: K learned-hybrid steps through the two-stream pipeline,
-    # with the BP occupancy cap that leaves the list decoder most room (tuned
-    # beforehand, untimed)
+    # with the list decoder's LDS budget and the caps on BP and list-decoder
+    # workgroups per CU that run it fastest (tuned beforehand, untimed)
     from paper_1609_09358_amd import autotune
     occ = autotune.tune_pipeline(learned_pipe, llr)
     elapsed = run_pipe(learned_pipe, out, args.steps, args.warmup)
@@ -291,6 +291,7 @@ def main():
     occ_p = autotune.tune_pipeline(plain_pipe, llr)
     gbps_plain = B * K * args.steps / run_pipe(plain_pipe, out_p, args.steps, args.warmup) / 1e9
     PB.polar_set_pipeline_bp_occupancy(0)
+    PB.polar_set_pipeline_scl_occupancy(0)
     gbps_plain_single = B * K * args.steps / run_steps(plain, out_p, args.steps, args.warmup) / 1e9
     # the learned decoder's list-decoder settings for what follows (kernel timing)
     PB.polar_set_scl_lds_budget(occ["lds_budget"])

@@ -271,6 +271,13 @@ polar_status polar_pipeline_workspace_size(const polar_code* code, int64_t B, in
  * Process-wide; host only. */
 polar_status polar_set_pipeline_bp_occupancy(int32_t wgs_per_cu);
 int32_t polar_get_pipeline_bp_occupancy(void);
+/* Workgroups per CU the pipelined hybrid's list decoder may run (1..64), or 0
+ * (the default) for as many as its registers and LDS allow on a CU.  The
+ * persistent list-decoder workgroups then walk the queue of failed frames in
+ * fewer, longer runs beside the next batch's BP; results are the same for every
+ * setting.  Only hybrid_decode_pipelined reads it.  Process-wide; host only. */
+polar_status polar_set_pipeline_scl_occupancy(int32_t wgs_per_cu);
+int32_t polar_get_pipeline_scl_occupancy(void);
 
 /* ---------------------------------------------------------------------------
  * Ragged batches that mix several codes (block lengths and rates): the

@@ -184,23 +184,30 @@ def tune_pipeline_occupancy(pipe: PB.HybridPipeline, llr: torch.Tensor, choices=
 
 
 def tune_pipeline(pipe: PB.HybridPipeline, llr: torch.Tensor, budgets=(0, 12288, 14336, 16384, 20480),
-                  caps=(0, 4, 6, 8), steps: int = 6) -> dict:
+                  caps=(0, 4, 6, 8), scl_caps=(0, 4, 6), steps: int = 6) -> dict:
     """The two-stream hybrid's launch settings: first the list decoder's LDS
     budget per workgroup (polar_set_scl_lds_budget; 0 = the automatic share,
-    a CU's LDS over the workgroups its registers allow), with no BP cap, then
-    the cap on BP workgroups per CU with the best budget; both timed over
-    `steps` batches of `llr` and left set.  The list decoder's LDS competes
-    with the BP workgroups beside it: a larger budget keeps more of its state
-    (the trace, then tree levels) out of the global slice, a smaller one leaves
+    a CU's LDS over the workgroups its registers allow) together with the cap
+    on list-decoder workgroups per CU (polar_set_pipeline_scl_occupancy; 0 =
+    all that fit), with no BP cap, then the cap on BP workgroups per CU with
+    the best pair; each setting timed over `steps` batches of `llr` (the
+    pairs as the best of three such runs: they differ by about 1 %) and the
+    best left set.  The list decoder's LDS competes with the BP workgroups
+    beside it: a larger budget keeps more of its state (the trace, then tree
+    levels) out of the global slice, a smaller one or a cap on its grid leaves
     room for more BP workgroups.  Results are the same for every setting.
-    Returns {"lds_budget": b, "wgs_per_cu": c, "ms_budget": {...}, "ms_cap": {...}}."""
+    Returns {"lds_budget": b, "scl_wgs_per_cu": s, "wgs_per_cu": c,
+    "ms_budget_scl_cap": {"b/s": ms}, "ms_cap": {c: ms}}."""
     PB.polar_set_pipeline_bp_occupancy(0)
     tb = {}
     for b in budgets:
         PB.polar_set_scl_lds_budget(b)
-        tb[b] = _time_pipe(pipe, llr, steps)
-    best_b = min(tb, key=tb.get)
+        for c in scl_caps:
+            PB.polar_set_pipeline_scl_occupancy(c)
+            tb[(b, c)] = min(_time_pipe(pipe, llr, steps) for _ in range(3))
+    best_b, best_s = min(tb, key=tb.get)
     PB.polar_set_scl_lds_budget(best_b)
+    PB.polar_set_pipeline_scl_occupancy(best_s)
     occ = tune_pipeline_occupancy(pipe, llr, caps, steps)
-    return {"lds_budget": int(best_b), "wgs_per_cu": occ["wgs_per_cu"],
-            "ms_budget": {int(k): round(v, 4) for k, v in tb.items()}, "ms_cap": occ["ms"]}
+    return {"lds_budget": int(best_b), "scl_wgs_per_cu": int(best_s), "wgs_per_cu": occ["wgs_per_cu"],
+            "ms_budget_scl_cap": {f"{b}/{c}": round(v, 4) for (b, c), v in tb.items()}, "ms_cap": occ["ms"]}

@@ -76,6 +76,7 @@ def lib():
             "wbp_column_grad": [vp, vp, i32, vp, vp],
             "polar_set_scl_lds_budget": [i64],
             "polar_set_pipeline_bp_occupancy": [i32],
+            "polar_set_pipeline_scl_occupancy": [i32],
             "polar_set_scl_ranking": [i32],
             "hybrid_decode_pipelined": [vp, i64, vp, i64, C.POINTER(bp_params), i32, vp, vp, vp, vp, sz, vp, vp],
             "polar_pipeline_workspace_size": [vp, i64, i32, C.POINTER(bp_params), C.POINTER(sz)],
@@ -95,6 +96,8 @@ def lib():
         L.polar_get_scl_ranking.restype = i32
         L.polar_get_pipeline_bp_occupancy.argtypes = []
         L.polar_get_pipeline_bp_occupancy.restype = i32
+        L.polar_get_pipeline_scl_occupancy.argtypes = []
+        L.polar_get_pipeline_scl_occupancy.restype = i32
         L.polar_get_scl_lds_budget.argtypes = []
         L.polar_get_scl_lds_budget.restype = i64
         L.polar_mixed_free.argtypes = [vp]
@@ -282,6 +285,16 @@ def polar_set_pipeline_bp_occupancy(wgs_per_cu: int):
 
 def polar_get_pipeline_bp_occupancy() -> int:
     return int(lib().polar_get_pipeline_bp_occupancy())
+
+
+def polar_set_pipeline_scl_occupancy(wgs_per_cu: int):
+    """List-decoder workgroups per CU in the pipelined hybrid (0 = as many as
+    fit); process-wide."""
+    _check(lib().polar_set_pipeline_scl_occupancy(int(wgs_per_cu)))
+
+
+def polar_get_pipeline_scl_occupancy() -> int:
+    return int(lib().polar_get_pipeline_scl_occupancy())
 
 
 def scl_decode_batch(code: PolarCode, llr: torch.Tensor, L, frame_ids=None, out=None, workspace=None):
@@ -620,5 +633,6 @@ EXPORTED = ["polar_last_error", "polar_build_code", "polar_construct_frozen", "p
             "wbp_backward", "wbp_bce_multi", "wbp_frame_loss", "wbp_iteration_loss", "wbp_column_weights", "wbp_column_grad",
             "polar_adam_step", "polar_adam_step_bounded", "polar_set_scl_lds_budget", "polar_get_scl_lds_budget",
             "hybrid_decode_pipelined", "polar_pipeline_workspace_size", "polar_set_pipeline_bp_occupancy",
-            "polar_get_pipeline_bp_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",
+            "polar_get_pipeline_bp_occupancy", "polar_set_pipeline_scl_occupancy",
+            "polar_get_pipeline_scl_occupancy", "polar_set_scl_ranking", "polar_get_scl_ranking", "polar_mixed_create", "polar_mixed_decode",
             "polar_mixed_decode_graph", "polar_mixed_free"]

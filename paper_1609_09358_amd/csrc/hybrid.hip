@@ -141,8 +141,9 @@ size_t carve(const polar_code* code, int64_t B, const SclPlan& plan, void* base,
     return off;
 }
 
-// BP workgroups per CU in the pipelined hybrid (0: no limit)
+// BP and list-decoder workgroups per CU in the pipelined hybrid (0: no limit)
 std::atomic<int> g_pipe_bp_wgs{0};
+std::atomic<int> g_pipe_scl_wgs{0};
 
 // per-batch states in flight in the pipelined hybrid: batch j + kPipeSlots
 // reuses batch j's state, so its BP waits for batch j's merge (three states
@@ -469,6 +470,12 @@ extern "C" polar_status hybrid_decode_pipelined(const polar_code* code, int64_t 
     if (st != POLAR_OK) return st;
     SclPlan plan;
     if ((st = scl_plan(code, L, B > 0 ? B : 1, &plan)) != POLAR_OK) return st;
+    // fewer persistent list-decoder workgroups (each walks more of the queue)
+    // use fewer global slices, so the workspace size query stays an upper bound
+    if (const int cap_wgs = g_pipe_scl_wgs.load(); cap_wgs > 0) {
+        const int64_t cap = (int64_t)device_cu_count() * cap_wgs;
+        if (plan.grid > cap) plan.grid = (int)(cap > 0 ? cap : 1);
+    }
     const size_t need = carve(code, B, plan, nullptr, nullptr, kPipeSlots);
     if (!ws || ws_bytes < need) return set_error(POLAR_ERR_WORKSPACE, "hybrid_decode_pipelined: workspace too small");
     if (nbatch == 0 || B == 0) return ok_status();
@@ -506,3 +513,12 @@ extern "C" polar_status polar_set_pipeline_bp_occupancy(int32_t wgs_per_cu) {
 }
 
 extern "C" int32_t polar_get_pipeline_bp_occupancy(void) { return g_pipe_bp_wgs.load(); }
+
+extern "C" polar_status polar_set_pipeline_scl_occupancy(int32_t wgs_per_cu) {
+    if (wgs_per_cu < 0 || wgs_per_cu > 64)
+        return set_error(POLAR_ERR_INVALID_ARG, "polar_set_pipeline_scl_occupancy: must be in [0, 64]");
+    g_pipe_scl_wgs.store(wgs_per_cu);
+    return ok_status();
+}
+
+extern "C" int32_t polar_get_pipeline_scl_occupancy(void) { return g_pipe_scl_wgs.load(); }

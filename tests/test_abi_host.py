@@ -93,6 +93,17 @@ def test_pipeline_bp_occupancy_setter():
     assert PB.polar_get_pipeline_bp_occupancy() == 0
 
 
+def test_pipeline_scl_occupancy_setter():
+    lib = PB.lib()
+    assert PB.polar_get_pipeline_scl_occupancy() == 0
+    assert lib.polar_set_pipeline_scl_occupancy(-1) == 1
+    assert lib.polar_set_pipeline_scl_occupancy(65) == 1
+    PB.polar_set_pipeline_scl_occupancy(4)
+    assert PB.polar_get_pipeline_scl_occupancy() == 4
+    PB.polar_set_pipeline_scl_occupancy(0)
+    assert PB.polar_get_pipeline_scl_occupancy() == 0
+
+
 def test_scl_ranking_setter():
     lib = PB.lib()
     assert PB.polar_get_scl_ranking() == 0

@@ -10,6 +10,7 @@ paper's 32-bit precision on both sides, same operation order); soft outputs
 match the float64 build within |a - b| <= 1e-4 * max(1, |b|).
 """
 import ctypes as C
+import functools
 
 import numpy as np
 import pytest
@@ -505,6 +506,33 @@ def test_pipelined_hybrid_with_capped_bp_grid(occ):
                 assert torch.equal(o["info"], ref["info"])
     finally:
         PB.polar_set_pipeline_bp_occupancy(0)
+
+
+@functools.lru_cache(maxsize=None)
+def _many_failures(N, K, c, ebn0, B):
+    """Frames at an Eb/N0 where 20 BP iterations fail on most of them, with the
+    oracle's hybrid (min-sum BP, CA-SCL L = 8) decisions."""
+    code, info, u, x, llr = frames(N, K, c, 2.5, ebn0, B, seed=N + 31)
+    ref = O.hybrid_batch(llr, code.frozen, K, c, POLY[c], 20, 8, prec="f32")
+    return code, llr, ref
+
+
+@pytest.mark.parametrize("occ", [1, 4])
+def test_pipelined_hybrid_with_capped_scl_grid(occ):
+    """With the list decoder's grid capped, each persistent workgroup walks
+    several failed frames of the queue; every batch still decodes as the
+    oracle's hybrid (more failed frames than the cap's workgroups on 256 CUs)."""
+    PB.polar_set_pipeline_scl_occupancy(occ)
+    try:
+        for N, K, c, ebn0, B in ((128, 64, 8, 0.5, 6000), (1024, 512, 24, 1.5, 1500)):
+            code, llr, ref = _many_failures(N, K, c, ebn0, B)
+            assert int(ref["used_scl"].sum()) > 256 * occ
+            outs = PB.HybridPipeline(code, max_iter=20, L=8)([dev(llr)] * 3, want_used=True)
+            for o in outs:
+                assert np.array_equal(host(o["used_scl"]), ref["used_scl"])
+                assert np.array_equal(host(o["info"]), ref["info"])
+    finally:
+        PB.polar_set_pipeline_scl_occupancy(0)
 
 
 @pytest.mark.parametrize("mode", [1, 2, 3])
