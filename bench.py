@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the per-kernel timing loops of the learned BP and the list decoder (for profilers)")
+    ap.add_argument("--profile-pipeline", action="store_true",
+                    help="only the headline's tuning and its K pipelined steps (for kernel traces)")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline, its FER check and per-kernel timing (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -209,7 +211,7 @@ def main():
                     "val_plain_min_sum": val_stats(torch.ones_like(W)), "val_alpha": val_stats(W0),
                     "val_frame_loss": val_stats(W_frame), "val_trained": val_stats(W)}
     del W_frame
-    if not args.profile_kernels:
+    if not (args.profile_kernels or args.profile_pipeline):
         t_s = time.perf_counter()
         Ws1, _ = TW.refine_blocks(code, val_llr, W0.clone(), wmax=1.0, stop=STOP)
         Ws, _ = TW.refine_blocks(code, val_llr, Ws1, per_column=True, wmax=1.0, stop=STOP)
@@ -277,6 +279,19 @@ def main():
         pipe([llr] * steps, outs=alt(steps))
         torch.cuda.synchronize()
         return time.perf_counter() - t0
+
+    if args.profile_pipeline:
+        # only the headline's pipelined steps (for rocprofv3 kernel traces): the
+        # untimed tuning, then W + K steps of the learned hybrid, the last K timed
+        from paper_1609_09358_amd import autotune
+        occ = autotune.tune_pipeline(learned_pipe, llr)
+        elapsed = run_pipe(learned_pipe, out, args.steps, args.warmup)
+        print(json.dumps(dict(steps=args.steps, warmup=args.warmup, frames=B,
+                              ms_per_step=round(1e3 * elapsed / args.steps, 4),
+                              Gbps=round(B * K * args.steps / elapsed / 1e9, 3),
+                              lds_budget=occ["lds_budget"], scl_wgs_per_cu=occ["scl_wgs_per_cu"],
+                              bp_wgs_per_cu=occ["wgs_per_cu"])))
+        return
 
     # ---- timed region: K learned-hybrid steps through the two-stream pipeline,
     # with the list decoder's LDS budget and the caps on BP and list-decoder
